@@ -1,0 +1,158 @@
+"""Closed-form reference values for the discrete Dean--Kawasaki scheme (numpy, no oracle).
+
+These are consequences of the paper's statements, computed in Fourier space, and serve as
+pins for the oracle (they share no code with it):
+
+* the noise-free scheme is rho^{m+1} = A rho^m with A = I + (tau/2) Lap_h, whose Fourier
+  multiplier is g_k = 1 - 2 mu (sin^2(pi k1/n) + sin^2(pi k2/n)) (Appendix A, operator A_h
+  with b0 = 0, b1 = 1);
+* Lemma "lem_Discrete_Martingale": (rho^m, A^{M-m} phi)_h is a martingale, hence
+  E<rho^M, phi>_h = <A^M rho^0, phi>_h for every N (the noise increments have mean 0);
+* the martingale increments are orthogonal, which gives
+  E[X^2] = sum_m tau (E[rho^m]^+, |grad_h phi^{m+1}|^2)_h for X = sqrt(N)(rho^M - rho_bar^M, phi)_h
+  (with equality to the mean-field value when rho stays positive);
+* for the NN coupling of Sec. 3.2 the same computation on the pair gives the level
+  variance of eq. (eqn:VarOfLvlPrelim) with rho replaced by the mean field.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import dk_workloads as W
+
+
+def grid(n: int, box: float):
+    x = np.arange(n) * (box / n)
+    X, Y = np.meshgrid(x, x)      # arrays indexed [y, x]
+    return X, Y
+
+
+def field_np(f: W.Field, box: float, n: int) -> np.ndarray:
+    X, Y = grid(n, box)
+    v = np.full((n, n), f.c0, dtype=np.float64)
+    if f.kind in (W.FIELD_MODES, W.FIELD_CLIPPED):
+        for m in f.modes:
+            v = v + m.amp * np.cos(2 * math.pi * (m.kx * X + m.ky * Y) / box + m.phase)
+        if f.kind == W.FIELD_CLIPPED:
+            v = np.maximum(v, 0.0) + f.floor_add
+        return v
+    if f.kind == W.FIELD_BUMP:
+        dx = np.abs(X - f.bump_cx) % box
+        dx = np.minimum(dx, box - dx)
+        dy = np.abs(Y - f.bump_cy) % box
+        dy = np.minimum(dy, box - dy)
+        return v + f.bump_amp * np.exp(-(dx * dx + dy * dy) / (2 * f.bump_sigma ** 2))
+    if f.kind == W.FIELD_EXPSIN2:
+        sx = np.sin(X - f.es_x0)
+        sy = np.sin(Y - f.es_y0)
+        return f.es_scale * (f.es_a + f.es_b * np.exp(-(sx * sx + sy * sy) / (2 * f.es_s)))
+    raise ValueError(f.kind)
+
+
+def heat_multiplier(n: int, mu: float) -> np.ndarray:
+    k = np.arange(n)
+    s = np.sin(math.pi * k / n) ** 2
+    return 1.0 - 2.0 * mu * (s[None, :] + s[:, None])
+
+
+def A_pow(f: np.ndarray, m: int, mu: float) -> np.ndarray:
+    lam = heat_multiplier(f.shape[0], mu)
+    return np.real(np.fft.ifft2(np.fft.fft2(f) * lam ** m))
+
+
+def grad(f: np.ndarray, h: float, flux: int):
+    """Adjoint partner of the divergence: central gradient for the central divergence,
+    forward gradient for the staggered one.  Returns (d/dx, d/dy) on [y, x] arrays."""
+    if flux == W.FLUX_CENTRAL:
+        gx = (np.roll(f, -1, axis=1) - np.roll(f, 1, axis=1)) / (2 * h)
+        gy = (np.roll(f, -1, axis=0) - np.roll(f, 1, axis=0)) / (2 * h)
+    else:
+        gx = (np.roll(f, -1, axis=1) - f) / h
+        gy = (np.roll(f, -1, axis=0) - f) / h
+    return gx, gy
+
+
+def mobility(rho: np.ndarray, flux: int):
+    """[rho]^+ where the noise of direction r is applied (node, or edge average)."""
+    if flux == W.FLUX_CENTRAL:
+        r = np.maximum(rho, 0.0)
+        return r, r
+    rx = np.maximum(0.5 * (rho + np.roll(rho, -1, axis=1)), 0.0)
+    ry = np.maximum(0.5 * (rho + np.roll(rho, -1, axis=0)), 0.0)
+    return rx, ry
+
+
+def linear_mean(p: W.Problem, level: int, phi: W.Field) -> float:
+    n, h = p.n(level), p.h(level)
+    rho0 = field_np(p.rho0, p.box, n)
+    return float(h * h * np.sum(A_pow(rho0, p.steps(level), p.mu) * field_np(phi, p.box, n)))
+
+
+def fluct_second_moment(p: W.Problem, level: int, phi: W.Field, flux: int | None = None) -> float:
+    """S_l = sum_{m<M} tau (rho_bar^m, |grad_h phi^{m+1}|^2)_h : E[X^2] of the centred,
+    sqrt(N)-scaled linear observable in the high-density limit (exact lower bound)."""
+    flux = p.flux if flux is None else flux
+    n, h, tau, M = p.n(level), p.h(level), p.tau(level), p.steps(level)
+    lam = heat_multiplier(n, p.mu)
+    r0 = np.fft.fft2(field_np(p.rho0, p.box, n))
+    f0 = np.fft.fft2(field_np(phi, p.box, n))
+    S = 0.0
+    for m in range(M):
+        rho = np.real(np.fft.ifft2(r0 * lam ** m))
+        ph = np.real(np.fft.ifft2(f0 * lam ** (M - m - 1)))
+        gx, gy = grad(ph, h, flux)
+        mx, my = mobility(rho, flux)
+        S += tau * h * h * float(np.sum(mx * gx * gx + my * gy * gy))
+    return S
+
+
+def pair_variance_linear(p: W.Problem, level: int, phi: W.Field, flux: int | None = None) -> float:
+    """Var(X_f - X_c) for the centred, sqrt(N)-scaled linear observable of the NN-coupled
+    pair (fine level l, coarse l-1) in the high-density limit: the cross-variation
+    structure of eq. (eqn:VarOfLvlPrelim) summed over fine steps.  Fine site y = (x, y)
+    belongs to the coarse cell (x // 2, y // 2) (right-most block B->)."""
+    flux = p.flux if flux is None else flux
+    nf, nc = p.n(level), p.n(level - 1)
+    hf, hc = p.h(level), p.h(level - 1)
+    tf = p.tau(level)
+    Mf = p.steps(level)
+    Mc = Mf // 4
+    lamf, lamc = heat_multiplier(nf, p.mu), heat_multiplier(nc, p.mu)
+    rf0 = np.fft.fft2(field_np(p.rho0, p.box, nf))
+    rc0 = np.fft.fft2(field_np(p.rho0, p.box, nc))
+    ff0 = np.fft.fft2(field_np(phi, p.box, nf))
+    fc0 = np.fft.fft2(field_np(phi, p.box, nc))
+    V = 0.0
+    coarse_cache = {}
+    for m in range(Mf):
+        mc = m // 4
+        if mc not in coarse_cache:
+            rc = np.real(np.fft.ifft2(rc0 * lamc ** mc))
+            phc = np.real(np.fft.ifft2(fc0 * lamc ** (Mc - mc - 1)))
+            gcx, gcy = grad(phc, hc, flux)
+            mcx, mcy = mobility(rc, flux)
+            ax = np.sqrt(mcx) * gcx
+            ay = np.sqrt(mcy) * gcy
+            # lift to the fine grid: fine (x, y) -> coarse (x//2, y//2)
+            coarse_cache = {mc: (np.kron(ax, np.ones((2, 2))), np.kron(ay, np.ones((2, 2))))}
+        cx, cy = coarse_cache[mc]
+        rf = np.real(np.fft.ifft2(rf0 * lamf ** m))
+        phf = np.real(np.fft.ifft2(ff0 * lamf ** (Mf - m - 1)))
+        gfx, gfy = grad(phf, hf, flux)
+        mfx, mfy = mobility(rf, flux)
+        dx = np.sqrt(mfx) * gfx - cx
+        dy = np.sqrt(mfy) * gfy - cy
+        V += tf * hf * hf * float(np.sum(dx * dx + dy * dy))
+    return V
+
+
+def one_step_sigma2(p: W.Problem, level: int, phi: W.Field, flux: int | None = None) -> float:
+    """Variance of X after exactly one step from a deterministic rho0: tau (rho0^+, |grad phi|^2)_h."""
+    flux = p.flux if flux is None else flux
+    n, h, tau = p.n(level), p.h(level), p.tau(level)
+    rho0 = field_np(p.rho0, p.box, n)
+    gx, gy = grad(field_np(phi, p.box, n), h, flux)
+    mx, my = mobility(rho0, flux)
+    return tau * h * h * float(np.sum(mx * gx * gx + my * gy * gy))
