@@ -1,0 +1,233 @@
+/*
+ * dk_mlmc.h -- C ABI of the MI355X (gfx950) MLMC Dean--Kawasaki hot path.
+ *
+ * Method: Cornalba & Fischer, "Multilevel Monte Carlo methods for the Dean--Kawasaki
+ * equation from Fluctuating Hydrodynamics" (arXiv 2311.08872).
+ *
+ *   discrete model     Definition "def_discrete_DK", eq. (FullyDiscreteDK), explicit
+ *                      Euler--Maruyama (b0 = 0, b1 = 1, Sec. 7), V = 0, d = 2
+ *   operators          5-point Laplacian and central divergence (Sec. 7, "Differential
+ *                      operators"); DK_FLUX_STAGGERED selects a forward difference of edge
+ *                      fluxes with the edge-averaged density under the square root
+ *   level hierarchy    h_l = box / (n0 2^l), tau_l = mu h_l^2 (eq. cfl_preserved),
+ *                      M_l = T / tau_l steps
+ *   coupling           NN ("Right-Most Nearest Neighbours"), Sec. 3.2: coarse Brownian
+ *                      increments are 2^{-d/2} times the sum of the fine increments over the
+ *                      2x2 right-most block and over the 4 fine steps of one coarse step
+ *   observables        P_l of eq. (eqn_MLMCLevels): psi( s ((rho_l^T, I_h phi)_h - c_l) ),
+ *                      c_l = (rho_bar_l^T, I_h phi)_h from the discrete mean field (Sec. 3)
+ *   estimator          eq. (MLMCEstimator) and Algorithm 1 (Sec. 7) with eq. (opt_M_ell)
+ *                      and eq. (convergence_criterion)
+ *
+ * Noise: Philox4x32-10 (Salmon et al., SC'11) keyed by the problem seed, with counter
+ *   (site pair a + (n/2) y, fine step m, sample bits 0..31,
+ *    tag << 24 | level << 16 | sample bits 32..47),
+ * followed by a Box--Muller transform evaluated as a fixed sequence of correctly rounded
+ * binary32 operations; words (0,1) give the two directions of site (2a, y), words (2,3)
+ * those of site (2a + 1, y).  The normals are therefore a pure function of
+ * (seed, tag, level, sample, site, step) and do not depend on launch shape or batching.
+ *
+ * Conventions for every entry point:
+ *   - all structs are caller-owned and only read during the call;
+ *   - "stream" is a hipStream_t passed as void* (NULL = the null stream); device outputs are
+ *     written stream-ordered; host outputs are complete when the call returns;
+ *   - return value: 0 = success, > 0 = warning with a valid result, < 0 = error (outputs
+ *     unspecified, inputs untouched); dk_last_error() describes the last error of the
+ *     calling thread;
+ *   - no C++ exception crosses this interface.
+ */
+#ifndef DK_MLMC_H
+#define DK_MLMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define DK_OK 0
+#define DK_WARN_NOT_CONVERGED 1   /* Algorithm 1 reached the last level without passing the bias test */
+#define DK_EINVAL (-1)            /* invalid argument or problem */
+#define DK_ENOMEM (-2)            /* device or host allocation failed */
+#define DK_EDEVICE (-3)           /* HIP runtime error */
+#define DK_ENUMERIC (-4)          /* non-finite sample values */
+#define DK_EUNSUPPORTED (-5)      /* valid request outside what this build implements */
+
+/* ---- enums ---- */
+#define DK_FIELD_MODES 0      /* c0 + sum amp cos(2 pi (kx x + ky y)/box + phase)            */
+#define DK_FIELD_CLIPPED 1    /* max(0, c0 + sum modes) + floor_add                            */
+#define DK_FIELD_BUMP 2       /* c0 + bump_amp exp(-|x - c|_per^2 / (2 sigma^2))               */
+#define DK_FIELD_EXPSIN2 3    /* es_scale (es_a + es_b exp(-(sin^2(x-x0) + sin^2(y-y0))/(2 es_s))) */
+
+#define DK_PSI_ID 0
+#define DK_PSI_SQUARE 1
+
+#define DK_FLUX_CENTRAL 0     /* central divergence of node fluxes (the paper's Sec. 7) */
+#define DK_FLUX_STAGGERED 1   /* forward divergence of edge fluxes                      */
+
+#define DK_STEPS_EXACT 0      /* EINVAL unless T / tau_0 is an integer            */
+#define DK_STEPS_ROUND_T 1    /* M_0 = round(T / tau_0); effective T = M_0 tau_0   */
+
+#define DK_PREC_F32 0         /* FP32 density state (default) */
+#define DK_PREC_F64 1         /* FP64 density state           */
+
+#define DK_TAG_MLMC 0         /* noise stream tags */
+#define DK_TAG_MC 1
+
+#define DK_MAX_OBS 64
+#define DK_MAX_LEVELS 12
+#define DK_MAX_MODES 64
+
+/* ---- problem statement (Sec. 2, Sec. 3, Sec. 7) ---- */
+typedef struct { double amp, kx, ky, phase; } dk_mode;
+
+typedef struct {
+    int32_t kind;             /* DK_FIELD_*                                */
+    int32_t n_modes;          /* <= DK_MAX_MODES                           */
+    double c0;
+    const dk_mode* modes;     /* host array [n_modes]                      */
+    double floor_add;
+    double bump_amp, bump_sigma, bump_cx, bump_cy;
+    double es_a, es_b, es_s, es_x0, es_y0, es_scale;
+} dk_field;
+
+typedef struct {
+    dk_field phi;             /* test function phi, evaluated at grid points (I_h)       */
+    int32_t centre;           /* 1: subtract (rho_bar_l^T, I_h phi)_h (discrete mean field) */
+    int32_t scale_sqrtN;      /* 1: multiply by N^{1/2}                                   */
+    int32_t psi;              /* DK_PSI_ID or DK_PSI_SQUARE                              */
+    int32_t reserved;
+} dk_obs;
+
+typedef struct {
+    int32_t d;                /* must be 2                                                 */
+    int32_t n0;               /* points per axis on level 0 (even, >= 4)                  */
+    int32_t levels;           /* number of levels L_max + 1 (<= DK_MAX_LEVELS)            */
+    int32_t steps_policy;     /* DK_STEPS_*                                                */
+    double box;               /* torus side length                                          */
+    double mu;                /* tau_l / h_l^2, 0 < mu <= 1/d (explicit stability)          */
+    double T;                 /* final time                                                 */
+    double N;                 /* particle number, > 0                                       */
+    int32_t flux;             /* DK_FLUX_*                                                  */
+    int32_t precision;        /* DK_PREC_*                                                  */
+    int32_t n_obs;            /* 1 .. DK_MAX_OBS                                            */
+    int32_t primary_obs;      /* observable that drives Algorithm 1                         */
+    const dk_obs* obs;        /* host array [n_obs]                                         */
+    dk_field rho0;            /* initial mean-field profile; rho^0 = I_h rho0 on every level */
+    uint64_t seed;            /* Philox key                                                 */
+} dk_problem;
+
+/* ---- per-level moment sums ---- */
+#define DK_MOM_Y 0     /* sum of Y = P_fine - P_coarse (P_coarse = 0 on level 0 / plain MC) */
+#define DK_MOM_Y2 1
+#define DK_MOM_PF 2
+#define DK_MOM_PF2 3
+#define DK_MOM_PC 4
+#define DK_MOM_PC2 5
+#define DK_NMOM 6
+
+typedef struct {
+    uint64_t count;
+    double sum[DK_NMOM];      /* compensated sums: value = sum + comp */
+    double comp[DK_NMOM];
+} dk_moments;
+
+typedef struct {
+    int32_t m_pilot;          /* pilot samples per level (Algorithm 1's M-bar); default 1000     */
+    int32_t L_start;          /* first L (default 2)                                             */
+    double alpha;             /* weak order in the bias test (default 2)                          */
+    int32_t max_rounds;       /* safety cap on Algorithm-1 rounds (default 1000)                  */
+    int32_t plain_mc_level;   /* >= 0: run plain MC on this level instead of MLMC                 */
+    uint64_t max_samples;     /* cap on total samples of one level (0 = none)                     */
+} dk_mlmc_opts;
+
+typedef struct {
+    double estimate[DK_MAX_OBS];   /* MLMC (or MC) estimate of E[P_L] per observable           */
+    double var_est[DK_MAX_OBS];    /* estimator variance sum_l V_l / M_l per observable        */
+    double bias_est;               /* bias estimate of the primary observable (remainder term) */
+    double rmse_est;               /* sqrt(var_est[primary] + bias_est^2)                      */
+    int32_t L;                     /* finest level used                                         */
+    int32_t converged;             /* 1 if the bias test passed                                 */
+    int32_t rounds;                /* Algorithm-1 rounds                                        */
+    int32_t reserved;
+    uint64_t M[DK_MAX_LEVELS];     /* samples per level                                          */
+    double Yhat[DK_MAX_LEVELS];    /* mean of Y_l, primary observable                            */
+    double Vhat[DK_MAX_LEVELS];    /* unbiased variance of Y_l, primary observable               */
+    double cost[DK_MAX_LEVELS];    /* C_l = cell updates per sample                              */
+    double cell_updates;           /* total fine + coarse cell updates performed                 */
+    double wall_s;                 /* host wall time of the call                                 */
+} dk_mlmc_result;
+
+typedef struct dk_context dk_context;
+
+/* Create a context on HIP device `device` (owns device workspace, per-problem level tables,
+ * cached centring constants and tuning choices).  One context per host thread. */
+int dk_context_create(dk_context** out, int device);
+void dk_context_destroy(dk_context* ctx);
+
+/* One batch of level-l samples [first_sample, first_sample + n_samples) of the MLMC hierarchy:
+ * l = 0: single level-0 paths (Y = P_0); l >= 1: NN-coupled pairs (fine l, coarse l-1),
+ * Y = P_l - P_{l-1} (Sec. 3.2, eq. MLMCEstimator).  stream_tag selects an independent noise
+ * stream (DK_TAG_MLMC for the estimator).
+ *   sums_out        host, caller-owned [n_obs]; receives the moment sums of this batch.
+ *   per_sample_out  optional DEVICE pointer [n_samples][n_obs][2] of doubles
+ *                   (P_fine, P_coarse), or NULL.
+ * Samples of any batch split give the same per-sample values. */
+int dk_mlmc_level_pair(dk_context* ctx, const dk_problem* problem, int32_t level,
+                       uint64_t first_sample, uint64_t n_samples, uint32_t stream_tag,
+                       dk_moments* sums_out, double* per_sample_out, void* stream);
+
+/* Plain (single-level) Monte Carlo batch on level l (the baseline of Sec. 7): uncoupled
+ * paths with the DK_TAG_MC stream; per_sample_out as above with P_coarse = 0. */
+int dk_mc_level(dk_context* ctx, const dk_problem* problem, int32_t level,
+                uint64_t first_sample, uint64_t n_samples,
+                dk_moments* sums_out, double* per_sample_out, void* stream);
+
+/* Algorithm 1 of Sec. 7 to RMSE eps on the GPU (or plain MC when opts->plain_mc_level >= 0).
+ * opts may be NULL (defaults).  level_moments: optional host array [levels][n_obs].
+ * Returns DK_WARN_NOT_CONVERGED when the last level is reached without passing the bias test. */
+int dk_mlmc_estimate(dk_context* ctx, const dk_problem* problem, double eps,
+                     const dk_mlmc_opts* opts, dk_mlmc_result* out,
+                     dk_moments* level_moments, void* stream);
+
+/* Centring constants c_{l,j} = (rho_bar_l^M, I_h phi_j)_h of the discrete mean field
+ * (noise-free FP64 run of the scheme from I_h rho0, Sec. 3).  centre_out: host [n_obs];
+ * rho_out: optional DEVICE pointer [n_l * n_l] doubles (x fastest) for the final field. */
+int dk_meanfield(dk_context* ctx, const dk_problem* problem, int32_t level,
+                 double* centre_out, double* rho_out, void* stream);
+
+/* The standard normals of the generator: out (DEVICE, floats) [n_samples][n_steps][n][n][2],
+ * indexed [sample][step][y][x][direction], for samples first_sample.. and steps
+ * first_step.. of an n x n grid (n even) on level `level` with the given tag. */
+int dk_noise_dump(dk_context* ctx, uint64_t seed, uint32_t tag, int32_t level, int32_t n,
+                  uint64_t first_sample, uint32_t n_samples, int32_t first_step,
+                  int32_t n_steps, float* out, void* stream);
+
+/* Final density fields of a batch (for field-level checks): rho_f_out [n_samples][n_l^2] and,
+ * for coupled pairs, rho_c_out [n_samples][n_{l-1}^2], DEVICE, element type float for
+ * DK_PREC_F32 and double for DK_PREC_F64.  coupled = 0 runs uncoupled level-l paths. */
+int dk_level_fields(dk_context* ctx, const dk_problem* problem, int32_t level, int32_t coupled,
+                    uint64_t first_sample, uint64_t n_samples, uint32_t stream_tag,
+                    double* per_sample_out, void* rho_f_out, void* rho_c_out, void* stream);
+
+/* Host-only Algorithm 1 (Sec. 7) over a caller-supplied level sampler; no GPU is touched.
+ * The sampler adds `count` samples of level l starting at sample index `first` and writes
+ * sum Y and sum Y^2 (primary observable) into sums[0], sums[1]; it returns 0 or an error
+ * code, which aborts the run.  cost[l] is C_l.  result->M, Yhat, Vhat, L, converged,
+ * rounds, estimate[0], var_est[0], bias_est and rmse_est are filled. */
+typedef int (*dk_level_sampler)(void* user, int32_t level, uint64_t first, uint64_t count,
+                                double* sums);
+int dk_alg1_host(double eps, int32_t L_max, const double* cost, const dk_mlmc_opts* opts,
+                 dk_level_sampler sampler, void* user, dk_mlmc_result* out);
+
+/* Description of the last error on the calling thread (static storage, never NULL). */
+const char* dk_last_error(void);
+
+/* Library version string. */
+const char* dk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DK_MLMC_H */

@@ -1,0 +1,274 @@
+"""MI355X (gfx950) MLMC for the Dean--Kawasaki equation: Python binding of libdk_mlmc.so.
+
+Every computation runs in the HIP library; this module only marshals arguments.  PyTorch is
+used for device buffers and streams.  The function names follow the C ABI
+(include/dk_mlmc.h): ``level_pair`` (dk_mlmc_level_pair), ``mc_level`` (dk_mc_level),
+``estimate`` (dk_mlmc_estimate), ``meanfield`` (dk_meanfield), ``noise_dump``
+(dk_noise_dump), ``level_fields`` (dk_level_fields) and ``alg1_host`` (dk_alg1_host).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Callable, List, Optional
+
+import numpy as np
+
+import dk_workloads as W
+
+from . import _lib as L
+
+__all__ = ["Context", "Moments", "level_pair", "mc_level", "estimate", "meanfield", "noise_dump",
+           "level_fields", "alg1_host", "DKError"]
+
+
+class DKError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"dk error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise DKError(rc, L.load().dk_last_error().decode(errors="replace"))
+    return rc
+
+
+# ------------------------------------------------------------------------------------------
+# Problem marshalling
+# ------------------------------------------------------------------------------------------
+
+def _field(f: W.Field, keep: list) -> L.dk_field:
+    n = len(f.modes)
+    arr = (L.dk_mode * max(n, 1))()
+    for i, m in enumerate(f.modes):
+        arr[i] = L.dk_mode(m.amp, m.kx, m.ky, m.phase)
+    keep.append(arr)
+    return L.dk_field(f.kind, n, f.c0, C.cast(arr, C.POINTER(L.dk_mode)), f.floor_add, f.bump_amp, f.bump_sigma,
+                      f.bump_cx, f.bump_cy, f.es_a, f.es_b, f.es_s, f.es_x0, f.es_y0, f.es_scale)
+
+
+class CProblem:
+    """A dk_problem struct (and the arrays it points to) built from a dk_workloads.Problem."""
+
+    def __init__(self, p: W.Problem):
+        self.p = p
+        self._keep = []
+        obs = (L.dk_obs * max(len(p.obs), 1))()
+        for i, o in enumerate(p.obs):
+            obs[i] = L.dk_obs(_field(o.phi, self._keep), int(o.centre), int(o.scale_sqrtN), int(o.psi), 0)
+        self._keep.append(obs)
+        self.c = L.dk_problem(2, p.n0, p.levels, p.steps_policy, p.box, p.mu, p.T, p.N, p.flux, p.precision,
+                              len(p.obs), p.primary, C.cast(obs, C.POINTER(L.dk_obs)), _field(p.rho0, self._keep),
+                              p.seed)
+
+    @property
+    def ref(self):
+        return C.byref(self.c)
+
+
+def _cp(problem) -> CProblem:
+    return problem if isinstance(problem, CProblem) else CProblem(problem)
+
+
+@dataclass
+class Moments:
+    count: int
+    sums: np.ndarray   # [DK_NMOM]: Y, Y^2, Pf, Pf^2, Pc, Pc^2 (compensated values)
+
+    @property
+    def mean(self) -> float:
+        return self.sums[0] / self.count
+
+    @property
+    def var(self) -> float:
+        n = self.count
+        m = self.sums[0] / n
+        return max(0.0, (self.sums[1] - n * m * m) / (n - 1)) if n > 1 else 0.0
+
+
+def _moments(arr) -> List[Moments]:
+    out = []
+    for m in arr:
+        out.append(Moments(int(m.count), np.array([m.sum[k] + m.comp[k] for k in range(L.DK_NMOM)])))
+    return out
+
+
+# ------------------------------------------------------------------------------------------
+# Context and streams
+# ------------------------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self.lib = L.load()
+        self.device = device
+        h = C.c_void_p()
+        _check(self.lib.dk_context_create(C.byref(h), device))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            self.lib.dk_context_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stream(self):
+        torch = _torch()
+        return C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+
+_default_ctx: Optional[Context] = None
+
+
+def default_context() -> Context:
+    global _default_ctx
+    if _default_ctx is None:
+        _default_ctx = Context(0)
+    return _default_ctx
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+# ------------------------------------------------------------------------------------------
+# Entry points
+# ------------------------------------------------------------------------------------------
+
+def level_pair(problem, level: int, first: int, n: int, tag: int = W.TAG_MLMC, per_sample: bool = False,
+               ctx: Context | None = None):
+    """dk_mlmc_level_pair: moments per observable, and optionally the per-sample (P_f, P_c)
+    as a float64 device tensor of shape (n, n_obs, 2)."""
+    ctx = ctx or default_context()
+    cp = _cp(problem)
+    nobs = len(cp.p.obs)
+    sums = (L.dk_moments * nobs)()
+    out = None
+    if per_sample:
+        torch = _torch()
+        out = torch.empty((n, nobs, 2), dtype=torch.float64, device=f"cuda:{ctx.device}")
+    _check(ctx.lib.dk_mlmc_level_pair(ctx.h, cp.ref, level, first, n, tag, sums, _ptr(out), ctx.stream()))
+    return (_moments(sums), out) if per_sample else _moments(sums)
+
+
+def mc_level(problem, level: int, first: int, n: int, per_sample: bool = False, ctx: Context | None = None):
+    ctx = ctx or default_context()
+    cp = _cp(problem)
+    nobs = len(cp.p.obs)
+    sums = (L.dk_moments * nobs)()
+    out = None
+    if per_sample:
+        torch = _torch()
+        out = torch.empty((n, nobs, 2), dtype=torch.float64, device=f"cuda:{ctx.device}")
+    _check(ctx.lib.dk_mc_level(ctx.h, cp.ref, level, first, n, sums, _ptr(out), ctx.stream()))
+    return (_moments(sums), out) if per_sample else _moments(sums)
+
+
+def _opts(m_pilot=1000, L_start=2, alpha=2.0, max_rounds=1000, plain_mc_level=-1, max_samples=0):
+    return L.dk_mlmc_opts(m_pilot, L_start, alpha, max_rounds, plain_mc_level, max_samples)
+
+
+def _result_dict(r: L.dk_mlmc_result, nobs: int, rc: int) -> dict:
+    Lv = r.L
+    return {"status": rc, "estimate": list(r.estimate[:nobs]), "var_est": list(r.var_est[:nobs]),
+            "bias_est": r.bias_est, "rmse_est": r.rmse_est, "L": Lv, "converged": bool(r.converged),
+            "rounds": r.rounds, "M": list(r.M[:Lv + 1]), "Yhat": list(r.Yhat[:Lv + 1]),
+            "Vhat": list(r.Vhat[:Lv + 1]), "cost": list(r.cost[:Lv + 1]), "cell_updates": r.cell_updates,
+            "wall_s": r.wall_s}
+
+
+def estimate(problem, eps: float, ctx: Context | None = None, level_moments: bool = False, **opts) -> dict:
+    """dk_mlmc_estimate: Algorithm 1 to RMSE eps (or plain MC with plain_mc_level=l)."""
+    ctx = ctx or default_context()
+    cp = _cp(problem)
+    nobs = len(cp.p.obs)
+    o = _opts(**opts)
+    r = L.dk_mlmc_result()
+    mom = (L.dk_moments * (cp.p.levels * nobs))() if level_moments else None
+    rc = _check(ctx.lib.dk_mlmc_estimate(ctx.h, cp.ref, eps, C.byref(o), C.byref(r), mom, ctx.stream()))
+    d = _result_dict(r, nobs, rc)
+    if level_moments:
+        ms = _moments(mom)
+        d["level_moments"] = [ms[l * nobs:(l + 1) * nobs] for l in range(cp.p.levels)]
+    return d
+
+
+def meanfield(problem, level: int, want_field: bool = False, ctx: Context | None = None):
+    ctx = ctx or default_context()
+    cp = _cp(problem)
+    nobs = len(cp.p.obs)
+    c = (C.c_double * nobs)()
+    rho = None
+    if want_field:
+        torch = _torch()
+        n = cp.p.n(level)
+        rho = torch.empty((n, n), dtype=torch.float64, device=f"cuda:{ctx.device}")
+    _check(ctx.lib.dk_meanfield(ctx.h, cp.ref, level, c, _ptr(rho), ctx.stream()))
+    cen = np.array(c[:])
+    return (cen, rho) if want_field else cen
+
+
+def noise_dump(seed: int, tag: int, level: int, n: int, first_sample: int, n_samples: int, first_step: int,
+               n_steps: int, ctx: Context | None = None):
+    """dk_noise_dump: float32 device tensor [n_samples, n_steps, n, n, 2] ([..., y, x, r])."""
+    ctx = ctx or default_context()
+    torch = _torch()
+    out = torch.empty((n_samples, n_steps, n, n, 2), dtype=torch.float32, device=f"cuda:{ctx.device}")
+    _check(ctx.lib.dk_noise_dump(ctx.h, seed, tag, level, n, first_sample, n_samples, first_step, n_steps,
+                                 _ptr(out), ctx.stream()))
+    return out
+
+
+def level_fields(problem, level: int, coupled: bool, first: int, n: int, tag: int = W.TAG_MLMC,
+                 ctx: Context | None = None):
+    """dk_level_fields: (per-sample (n, n_obs, 2), rho_f (n, nf, nf), rho_c (n, nc, nc) or None)."""
+    ctx = ctx or default_context()
+    torch = _torch()
+    cp = _cp(problem)
+    nobs = len(cp.p.obs)
+    dt = torch.float64 if cp.p.precision == W.PREC_F64 else torch.float32
+    nf = cp.p.n(level)
+    dev = f"cuda:{ctx.device}"
+    ps = torch.empty((n, nobs, 2), dtype=torch.float64, device=dev)
+    rf = torch.empty((n, nf, nf), dtype=dt, device=dev)
+    rc = torch.empty((n, nf // 2, nf // 2), dtype=dt, device=dev) if coupled else None
+    _check(ctx.lib.dk_level_fields(ctx.h, cp.ref, level, int(coupled), first, n, tag, _ptr(ps), _ptr(rf), _ptr(rc),
+                                   ctx.stream()))
+    return ps, rf, rc
+
+
+def alg1_host(eps: float, L_max: int, cost, sampler: Callable[[int, int, int], np.ndarray], **opts) -> dict:
+    """dk_alg1_host: the library's Algorithm 1 over a Python level sampler (no GPU).
+    sampler(level, first, count) returns the values Y of those samples."""
+    lib = L.load()
+    err = []
+
+    def cb(user, level, first, count, sums):
+        try:
+            y = np.asarray(sampler(int(level), int(first), int(count)), dtype=np.float64)
+            sums[0] = float(np.sum(y))
+            sums[1] = float(np.sum(y * y))
+            return 0
+        except Exception as e:   # reported as an error code through the ABI
+            err.append(e)
+            return -1
+
+    cfun = L.SAMPLER(cb)
+    carr = (C.c_double * (L_max + 1))(*[float(c) for c in cost])
+    o = _opts(**opts)
+    r = L.dk_mlmc_result()
+    rc = lib.dk_alg1_host(eps, L_max, carr, C.byref(o), cfun, None, C.byref(r))
+    if err:
+        raise err[0]
+    _check(rc)
+    return _result_dict(r, 1, rc)

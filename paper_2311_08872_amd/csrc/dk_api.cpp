@@ -1,0 +1,755 @@
+// dk_api.cpp -- host side of the C ABI: validation, level tables, batching into chunks,
+// the ordered moment reduction, Algorithm 1 of Sec. 7 and plain Monte Carlo.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "dk_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return fail(DK_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+// ------------------------------------------------------------------------------------------
+// Compensated accumulation on the host (Neumaier), used to merge ordered partial sums.
+// ------------------------------------------------------------------------------------------
+void nadd(double& s, double& c, double x)
+{
+    const double t = s + x;
+    if (std::fabs(s) >= std::fabs(x)) c += (s - t) + x;
+    else c += (x - t) + s;
+    s = t;
+}
+
+void merge_moments(dk_moments& dst, const double* part /* [DK_NMOM][2] */, uint64_t count)
+{
+    dst.count += count;
+    for (int k = 0; k < DK_NMOM; ++k) {
+        nadd(dst.sum[k], dst.comp[k], part[2 * k]);
+        dst.comp[k] += part[2 * k + 1];
+    }
+}
+
+double mom_value(const dk_moments& m, int k) { return m.sum[k] + m.comp[k]; }
+
+// ------------------------------------------------------------------------------------------
+// Problem hashing (FNV-1a over every field that changes results)
+// ------------------------------------------------------------------------------------------
+struct Hasher {
+    uint64_t h = 1469598103934665603ull;
+    void bytes(const void* p, size_t n)
+    {
+        const unsigned char* b = (const unsigned char*)p;
+        for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 1099511628211ull; }
+    }
+    template <class T> void val(const T& v) { bytes(&v, sizeof(T)); }
+    void field(const dk_field& f)
+    {
+        val(f.kind); val(f.n_modes); val(f.c0); val(f.floor_add);
+        val(f.bump_amp); val(f.bump_sigma); val(f.bump_cx); val(f.bump_cy);
+        val(f.es_a); val(f.es_b); val(f.es_s); val(f.es_x0); val(f.es_y0); val(f.es_scale);
+        for (int k = 0; k < f.n_modes; ++k) val(f.modes[k]);
+    }
+};
+
+uint64_t problem_hash(const dk_problem* p)
+{
+    Hasher H;
+    H.val(p->d); H.val(p->n0); H.val(p->levels); H.val(p->steps_policy); H.val(p->box); H.val(p->mu);
+    H.val(p->T); H.val(p->N); H.val(p->flux); H.val(p->precision); H.val(p->n_obs);
+    H.field(p->rho0);
+    for (int j = 0; j < p->n_obs; ++j) {
+        H.field(p->obs[j].phi); H.val(p->obs[j].centre); H.val(p->obs[j].scale_sqrtN); H.val(p->obs[j].psi);
+    }
+    return H.h;
+}
+
+int validate_field(const dk_field& f, const char* what)
+{
+    if (f.kind < DK_FIELD_MODES || f.kind > DK_FIELD_EXPSIN2) return fail(DK_EINVAL, "%s: unknown field kind %d", what, f.kind);
+    if (f.n_modes < 0 || f.n_modes > DK_MAX_MODES) return fail(DK_EINVAL, "%s: n_modes %d outside [0, %d]", what, f.n_modes, DK_MAX_MODES);
+    if (f.n_modes > 0 && !f.modes) return fail(DK_EINVAL, "%s: modes is NULL", what);
+    if (f.kind == DK_FIELD_BUMP && !(f.bump_sigma > 0)) return fail(DK_EINVAL, "%s: bump_sigma must be > 0", what);
+    if (f.kind == DK_FIELD_EXPSIN2 && !(f.es_s > 0)) return fail(DK_EINVAL, "%s: es_s must be > 0", what);
+    return DK_OK;
+}
+
+// steps on level 0, or a negative error code
+long steps0_of(const dk_problem* p)
+{
+    const double h0 = p->box / p->n0;
+    const double tau0 = p->mu * h0 * h0;
+    const double r = p->T / tau0;
+    const long m = std::lround(r);
+    if (m < 1) return fail(DK_EINVAL, "T / tau_0 = %g gives no time step", r);
+    if (p->steps_policy == DK_STEPS_EXACT && std::fabs(r - (double)m) > 1e-9 * std::max(1.0, r))
+        return fail(DK_EINVAL, "T / tau_0 = %.12g is not an integer (use DK_STEPS_ROUND_T)", r);
+    return m;
+}
+
+int validate(const dk_problem* p)
+{
+    if (!p) return fail(DK_EINVAL, "problem is NULL");
+    if (p->d != 2) return fail(DK_EUNSUPPORTED, "d = %d: only d = 2 is implemented", p->d);
+    if (p->n0 < 4 || (p->n0 & 1)) return fail(DK_EINVAL, "n0 = %d must be even and >= 4", p->n0);
+    if (p->levels < 1 || p->levels > DK_MAX_LEVELS) return fail(DK_EINVAL, "levels = %d outside [1, %d]", p->levels, DK_MAX_LEVELS);
+    if (!(p->box > 0)) return fail(DK_EINVAL, "box must be > 0");
+    if (!(p->mu > 0) || p->mu > 0.5 + 1e-12) return fail(DK_EINVAL, "mu = %g outside (0, 1/d]: the explicit scheme is unstable", p->mu);
+    if (!(p->T > 0)) return fail(DK_EINVAL, "T must be > 0");
+    if (!(p->N > 0)) return fail(DK_EINVAL, "N must be > 0");
+    if (p->flux != DK_FLUX_CENTRAL && p->flux != DK_FLUX_STAGGERED) return fail(DK_EINVAL, "unknown flux %d", p->flux);
+    if (p->precision != DK_PREC_F32 && p->precision != DK_PREC_F64) return fail(DK_EINVAL, "unknown precision %d", p->precision);
+    if (p->steps_policy != DK_STEPS_EXACT && p->steps_policy != DK_STEPS_ROUND_T) return fail(DK_EINVAL, "unknown steps_policy");
+    if (p->n_obs < 1 || p->n_obs > DK_MAX_OBS) return fail(DK_EINVAL, "n_obs = %d outside [1, %d]", p->n_obs, DK_MAX_OBS);
+    if (!p->obs) return fail(DK_EINVAL, "obs is NULL");
+    if (p->primary_obs < 0 || p->primary_obs >= p->n_obs) return fail(DK_EINVAL, "primary_obs out of range");
+    int rc = validate_field(p->rho0, "rho0");
+    if (rc) return rc;
+    for (int j = 0; j < p->n_obs; ++j) {
+        rc = validate_field(p->obs[j].phi, "obs.phi");
+        if (rc) return rc;
+        if (p->obs[j].psi != DK_PSI_ID && p->obs[j].psi != DK_PSI_SQUARE) return fail(DK_EINVAL, "obs %d: unknown psi", j);
+    }
+    const long m0 = steps0_of(p);
+    if (m0 < 0) return (int)m0;
+    const long mtop = m0 << (2 * (p->levels - 1));
+    if (mtop > (1l << 30)) return fail(DK_EINVAL, "too many time steps (%ld) on the finest level", mtop);
+    if ((long)p->n0 << (p->levels - 1) > 4096) return fail(DK_EINVAL, "finest grid larger than 4096");
+    return DK_OK;
+}
+
+dk::FieldDev to_dev(const dk_field& f)
+{
+    dk::FieldDev d;
+    std::memset(&d, 0, sizeof(d));
+    d.kind = f.kind; d.n_modes = f.n_modes; d.c0 = f.c0; d.floor_add = f.floor_add;
+    d.bump_amp = f.bump_amp; d.bump_sigma = f.bump_sigma; d.bump_cx = f.bump_cx; d.bump_cy = f.bump_cy;
+    d.es_a = f.es_a; d.es_b = f.es_b; d.es_s = f.es_s; d.es_x0 = f.es_x0; d.es_y0 = f.es_y0; d.es_scale = f.es_scale;
+    for (int k = 0; k < f.n_modes; ++k) {
+        d.amp[k] = f.modes[k].amp; d.kx[k] = f.modes[k].kx; d.ky[k] = f.modes[k].ky; d.phase[k] = f.modes[k].phase;
+    }
+    return d;
+}
+
+// device buffer owned by the context
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+    int ensure(size_t n)
+    {
+        if (n <= bytes) return DK_OK;
+        if (p) { (void)hipFree(p); p = nullptr; bytes = 0; }
+        if (hipMalloc(&p, n) != hipSuccess) return fail(DK_ENOMEM, "hipMalloc(%zu) failed", n);
+        bytes = n;
+        return DK_OK;
+    }
+};
+
+struct LevelTables {
+    int n = 0;
+    double h = 0, tau = 0;
+    long steps = 0;
+    DevBuf rho0;      // state type
+    DevBuf phi;       // double [n_obs][n*n]
+    DevBuf obs;       // double [n_obs][3] {scale, centre, psi}
+    std::vector<double> centre;   // c_{l,j} (0 where not centred)
+    bool have_centre = false;
+};
+
+struct ProblemTables {
+    std::vector<std::unique_ptr<LevelTables>> level;
+};
+
+}  // namespace
+
+struct dk_context {
+    int device = 0;
+    DevBuf per_sample;     // chunk buffer of per-sample outputs
+    DevBuf moments;        // [chunks][n_obs][DK_NMOM][2]
+    DevBuf mf0, mf1;       // mean-field streaming buffers
+    DevBuf scratch_c;      // inner products
+    std::vector<double> host_mom;
+    std::map<uint64_t, std::unique_ptr<ProblemTables>> problems;
+};
+
+namespace {
+
+double noise_coeff(const dk_problem* p, double h, double sigma)
+{
+    // N^{-1/2} h^{-d/2} sigma / (2h) (central) or N^{-1/2} h^{-d/2} sigma / h (staggered), d = 2
+    const double base = sigma / (std::sqrt(p->N) * h * h);
+    return p->flux == DK_FLUX_CENTRAL ? 0.5 * base : base;
+}
+
+int ensure_level(dk_context* ctx, const dk_problem* p, int level, LevelTables** out, hipStream_t s);
+
+int compute_centre(dk_context* ctx, const dk_problem* p, int level, LevelTables& T, hipStream_t s, double* rho_out)
+{
+    const int n = T.n;
+    const int nobs = p->n_obs;
+    std::vector<double> c(nobs, 0.0);
+    const double a = 0.5 * p->mu;
+    if (dk::level_supported(n)) {
+        // FP64 rho0 for the noise-free resident kernel
+        DevBuf r0;
+        int rc = r0.ensure(sizeof(double) * n * n);
+        if (rc) return rc;
+        HIP_TRY(dk::launch_field_eval(to_dev(p->rho0), p->box, n, r0.p, true, s));
+        rc = ctx->per_sample.ensure(sizeof(double) * 2 * nobs);
+        if (rc) return rc;
+        std::vector<double> obs_host(3 * nobs);
+        for (int j = 0; j < nobs; ++j) { obs_host[3 * j] = 1.0; obs_host[3 * j + 1] = 0.0; obs_host[3 * j + 2] = 0.0; }
+        DevBuf obs_unit;
+        rc = obs_unit.ensure(sizeof(double) * 3 * nobs);
+        if (rc) return rc;
+        HIP_TRY(hipMemcpyAsync(obs_unit.p, obs_host.data(), sizeof(double) * 3 * nobs, hipMemcpyHostToDevice, s));
+        dk::LevelArgs A{};
+        A.nf = n; A.level_id = level; A.tag = 0; A.seed = 0; A.first = 0; A.count = 1; A.steps = (int)T.steps;
+        A.a = a; A.kf = 0; A.kc = 0; A.h2f = T.h * T.h; A.h2c = 0;
+        A.rho0_f = r0.p; A.rho0_c = nullptr; A.phi_f = (const double*)T.phi.p; A.phi_c = nullptr;
+        A.obs_f = (const double*)obs_unit.p; A.obs_c = nullptr; A.n_obs = nobs;
+        A.out = (double*)ctx->per_sample.p; A.field_f = rho_out; A.field_c = nullptr;
+        dk::LevelKind K{DK_PREC_F64, false, DK_FLUX_CENTRAL, false};
+        HIP_TRY(dk::launch_level(K, A, s));
+        std::vector<double> res(2 * nobs);
+        HIP_TRY(hipMemcpyAsync(res.data(), ctx->per_sample.p, sizeof(double) * 2 * nobs, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int j = 0; j < nobs; ++j) c[j] = res[2 * j];
+    } else {
+        int rc = ctx->mf0.ensure(sizeof(double) * n * n);
+        if (rc) return rc;
+        rc = ctx->mf1.ensure(sizeof(double) * n * n);
+        if (rc) return rc;
+        rc = ctx->scratch_c.ensure(sizeof(double) * nobs);
+        if (rc) return rc;
+        HIP_TRY(dk::launch_field_eval(to_dev(p->rho0), p->box, n, ctx->mf0.p, true, s));
+        double* res = nullptr;
+        HIP_TRY(dk::launch_meanfield_stream(n, a, (int)T.steps, (double*)ctx->mf0.p, (double*)ctx->mf1.p, &res, s));
+        HIP_TRY(dk::launch_inner_products(res, n, (const double*)T.phi.p, nobs, T.h * T.h, (double*)ctx->scratch_c.p, s));
+        HIP_TRY(hipMemcpyAsync(c.data(), ctx->scratch_c.p, sizeof(double) * nobs, hipMemcpyDeviceToHost, s));
+        if (rho_out) HIP_TRY(hipMemcpyAsync(rho_out, res, sizeof(double) * n * n, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    T.centre = c;
+    T.have_centre = true;
+    return DK_OK;
+}
+
+int ensure_level(dk_context* ctx, const dk_problem* p, int level, LevelTables** out, hipStream_t s)
+{
+    const uint64_t key = problem_hash(p);
+    auto& slot = ctx->problems[key];
+    if (!slot) slot.reset(new ProblemTables());
+    ProblemTables& PT = *slot;
+    if ((int)PT.level.size() < p->levels) PT.level.resize(p->levels);
+    if (level < 0 || level >= p->levels) return fail(DK_EINVAL, "level %d outside [0, %d)", level, p->levels);
+    if (PT.level[level]) { *out = PT.level[level].get(); return DK_OK; }
+    std::unique_ptr<LevelTables> T(new LevelTables());
+    const int n = p->n0 << level;
+    T->n = n;
+    T->h = p->box / n;
+    T->tau = p->mu * T->h * T->h;
+    T->steps = steps0_of(p) << (2 * level);
+    const bool f64 = p->precision == DK_PREC_F64;
+    const int nobs = p->n_obs;
+    int rc = T->rho0.ensure((f64 ? 8 : 4) * (size_t)n * n);
+    if (rc) return rc;
+    HIP_TRY(dk::launch_field_eval(to_dev(p->rho0), p->box, n, T->rho0.p, f64, s));
+    rc = T->phi.ensure(sizeof(double) * (size_t)nobs * n * n);
+    if (rc) return rc;
+    for (int j = 0; j < nobs; ++j)
+        HIP_TRY(dk::launch_field_eval(to_dev(p->obs[j].phi), p->box, n, (double*)T->phi.p + (size_t)j * n * n, true, s));
+    bool any_centre = false;
+    for (int j = 0; j < nobs; ++j) any_centre |= p->obs[j].centre != 0;
+    if (any_centre) {
+        rc = compute_centre(ctx, p, level, *T, s, nullptr);
+        if (rc) return rc;
+    } else {
+        T->centre.assign(nobs, 0.0);
+    }
+    std::vector<double> obs_host(3 * nobs);
+    for (int j = 0; j < nobs; ++j) {
+        obs_host[3 * j + 0] = p->obs[j].scale_sqrtN ? std::sqrt(p->N) : 1.0;
+        obs_host[3 * j + 1] = p->obs[j].centre ? T->centre[j] : 0.0;
+        obs_host[3 * j + 2] = p->obs[j].psi == DK_PSI_SQUARE ? 1.0 : 0.0;
+    }
+    rc = T->obs.ensure(sizeof(double) * 3 * nobs);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(T->obs.p, obs_host.data(), sizeof(double) * 3 * nobs, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    PT.level[level] = std::move(T);
+    *out = PT.level[level].get();
+    return DK_OK;
+}
+
+constexpr uint64_t kMaxChunk = 1ull << 22;
+constexpr size_t kChunkBytes = 256ull << 20;
+
+uint64_t chunk_size(int n_obs)
+{
+    uint64_t c = kChunkBytes / (16ull * n_obs);
+    return std::min<uint64_t>(c, kMaxChunk);
+}
+
+// Run samples [first, first+count) of level `level` (coupled pair if `pair`), reduce the
+// per-sample values in chunk order and return per-observable moments.
+int run_level(dk_context* ctx, const dk_problem* p, int level, bool pair, uint64_t first, uint64_t count,
+              uint32_t tag, dk_moments* sums_out, double* per_sample_out, void* field_f, void* field_c,
+              hipStream_t s, double* cell_updates)
+{
+    int rc = validate(p);
+    if (rc) return rc;
+    if (pair && level < 1) return fail(DK_EINVAL, "a coupled pair needs level >= 1");
+    if (level < 0 || level >= p->levels) return fail(DK_EINVAL, "level %d outside [0, %d)", level, p->levels);
+    if (count > 0 && first + count < first) return fail(DK_EINVAL, "sample range overflows");
+    if (first + count > (1ull << 48)) return fail(DK_EINVAL, "sample index beyond 2^48");
+    const int nf = p->n0 << level;
+    if (!dk::level_supported(nf)) return fail(DK_EUNSUPPORTED, "grid %d x %d: no resident kernel for this size", nf, nf);
+    LevelTables* Tf = nullptr;
+    LevelTables* Tc = nullptr;
+    rc = ensure_level(ctx, p, level, &Tf, s);
+    if (rc) return rc;
+    if (pair) {
+        rc = ensure_level(ctx, p, level - 1, &Tc, s);
+        if (rc) return rc;
+    }
+    const int nobs = p->n_obs;
+    for (int j = 0; j < nobs; ++j) std::memset(&sums_out[j], 0, sizeof(dk_moments));
+    if (count == 0) return DK_OK;
+    const uint64_t ch = chunk_size(nobs);
+    const uint64_t nchunks = (count + ch - 1) / ch;
+    if (!per_sample_out) {
+        rc = ctx->per_sample.ensure(sizeof(double) * 2 * nobs * std::min<uint64_t>(ch, count));
+        if (rc) return rc;
+    }
+    const size_t mom_stride = (size_t)nobs * DK_NMOM * 2;
+    rc = ctx->moments.ensure(sizeof(double) * mom_stride * nchunks);
+    if (rc) return rc;
+
+    dk::LevelArgs A{};
+    A.nf = nf;
+    A.level_id = level;
+    A.tag = tag;
+    A.seed = p->seed;
+    A.steps = (int)Tf->steps;
+    A.a = 0.5 * p->mu;
+    const double sig_f = std::sqrt(Tf->tau);
+    A.kf = noise_coeff(p, Tf->h, sig_f);
+    A.kc = pair ? noise_coeff(p, Tc->h, 0.5 * sig_f) : 0.0;   // 2^{-d/2} sqrt(tau_f) per unit of the restricted sum
+    A.h2f = Tf->h * Tf->h;
+    A.h2c = pair ? Tc->h * Tc->h : 0.0;
+    A.rho0_f = Tf->rho0.p;
+    A.rho0_c = pair ? Tc->rho0.p : nullptr;
+    A.phi_f = (const double*)Tf->phi.p;
+    A.phi_c = pair ? (const double*)Tc->phi.p : nullptr;
+    A.obs_f = (const double*)Tf->obs.p;
+    A.obs_c = pair ? (const double*)Tc->obs.p : nullptr;
+    A.n_obs = nobs;
+    dk::LevelKind K{p->precision, pair, p->flux, true};
+    const size_t esize = p->precision == DK_PREC_F64 ? 8 : 4;
+    for (uint64_t k = 0; k < nchunks; ++k) {
+        const uint64_t b = k * ch;
+        const uint64_t c = std::min(ch, count - b);
+        A.first = first + b;
+        A.count = c;
+        A.out = per_sample_out ? per_sample_out + b * nobs * 2 : (double*)ctx->per_sample.p;
+        A.field_f = field_f ? (char*)field_f + b * esize * nf * nf : nullptr;
+        A.field_c = (field_c && pair) ? (char*)field_c + b * esize * (nf / 2) * (nf / 2) : nullptr;
+        HIP_TRY(dk::launch_level(K, A, s));
+        HIP_TRY(dk::launch_moments(A.out, c, nobs, (double*)ctx->moments.p + k * mom_stride, s));
+    }
+    ctx->host_mom.resize(mom_stride * nchunks);
+    HIP_TRY(hipMemcpyAsync(ctx->host_mom.data(), ctx->moments.p, sizeof(double) * mom_stride * nchunks,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (uint64_t k = 0; k < nchunks; ++k) {
+        const uint64_t c = std::min(ch, count - k * ch);
+        for (int j = 0; j < nobs; ++j) merge_moments(sums_out[j], &ctx->host_mom[k * mom_stride + j * DK_NMOM * 2], c);
+    }
+    for (int j = 0; j < nobs; ++j)
+        for (int m = 0; m < DK_NMOM; ++m)
+            if (!std::isfinite(mom_value(sums_out[j], m))) return fail(DK_ENUMERIC, "non-finite sample values on level %d", level);
+    if (cell_updates) {
+        const double per = (double)nf * nf * (double)Tf->steps * (pair ? 1.0 + 1.0 / 16.0 : 1.0);
+        *cell_updates += per * (double)count;
+    }
+    return DK_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Algorithm 1 (Sec. 7), independent of how samples are produced.
+// ------------------------------------------------------------------------------------------
+dk_mlmc_opts default_opts()
+{
+    dk_mlmc_opts o;
+    std::memset(&o, 0, sizeof(o));
+    o.m_pilot = 1000;
+    o.L_start = 2;
+    o.alpha = 2.0;
+    o.max_rounds = 1000;
+    o.plain_mc_level = -1;
+    o.max_samples = 0;
+    return o;
+}
+
+double bias_remainder(const std::vector<double>& Y, int L, double alpha)
+{
+    double r = 0.0;
+    for (int j = 0; j <= std::min(2, L); ++j) r = std::max(r, std::pow(2.0, -j * alpha) * std::fabs(Y[L - j]));
+    return r / (std::pow(2.0, alpha) - 1.0);
+}
+
+int alg1_core(double eps, int L_max, const double* cost, const dk_mlmc_opts& o, dk_level_sampler sampler, void* user,
+              dk_mlmc_result* out)
+{
+    if (!(eps > 0)) return fail(DK_EINVAL, "eps must be > 0");
+    if (L_max < 0 || L_max >= DK_MAX_LEVELS) return fail(DK_EINVAL, "L_max out of range");
+    if (o.m_pilot < 2) return fail(DK_EINVAL, "m_pilot must be >= 2");
+    for (int l = 0; l <= L_max; ++l)
+        if (!(cost[l] > 0)) return fail(DK_EINVAL, "cost[%d] must be > 0", l);
+    int L = std::min(std::max(o.L_start, 0), L_max);
+    std::vector<uint64_t> done(L_max + 1, 0), target(L_max + 1, 0);
+    std::vector<double> s1(L_max + 1, 0), c1(L_max + 1, 0), s2(L_max + 1, 0), c2(L_max + 1, 0);
+    for (int l = 0; l <= L; ++l) target[l] = (uint64_t)o.m_pilot;
+    std::vector<double> Y(L_max + 1, 0), V(L_max + 1, 0);
+    auto stats = [&](int upto) {
+        for (int l = 0; l <= upto; ++l) {
+            const double n = (double)done[l];
+            const double m1 = (s1[l] + c1[l]) / n;
+            Y[l] = m1;
+            V[l] = done[l] > 1 ? std::max(0.0, ((s2[l] + c2[l]) - n * m1 * m1) / (n - 1.0)) : 0.0;
+        }
+    };
+    int rounds = 0;
+    bool conv = false;
+    for (;;) {
+        bool need = false;
+        for (int l = 0; l <= L; ++l) need |= target[l] > done[l];
+        if (!need) {
+            stats(L);
+            if (L >= 2 || L == L_max) {
+                if (bias_remainder(Y, L, o.alpha) < eps / std::sqrt(2.0)) { conv = true; break; }
+            }
+            if (L == L_max) { conv = false; break; }
+            L += 1;
+            target[L] = (uint64_t)o.m_pilot;
+            continue;
+        }
+        if (rounds >= o.max_rounds) return fail(DK_EINVAL, "Algorithm 1 exceeded max_rounds = %d", o.max_rounds);
+        ++rounds;
+        for (int l = 0; l <= L; ++l) {
+            if (target[l] <= done[l]) continue;
+            const uint64_t extra = target[l] - done[l];
+            double sums[2] = {0, 0};
+            const int rc = sampler(user, l, done[l], extra, sums);
+            if (rc < 0) return rc;
+            if (!std::isfinite(sums[0]) || !std::isfinite(sums[1])) return fail(DK_ENUMERIC, "non-finite sums on level %d", l);
+            nadd(s1[l], c1[l], sums[0]);
+            nadd(s2[l], c2[l], sums[1]);
+            done[l] += extra;
+        }
+        stats(L);
+        double acc = 0.0;
+        for (int l = 0; l <= L; ++l) acc += std::sqrt(V[l] * cost[l]);
+        for (int l = 0; l <= L; ++l) {
+            const double m = std::ceil(2.0 / (eps * eps) * std::sqrt(V[l] / cost[l]) * acc);
+            uint64_t mi = m > 1.8e19 ? (uint64_t)1.8e19 : (uint64_t)m;
+            if (o.max_samples && mi > o.max_samples) mi = o.max_samples;
+            target[l] = std::max(done[l], mi);
+        }
+    }
+    stats(L);
+    std::memset(out, 0, sizeof(*out));
+    double est = 0.0, var = 0.0;
+    for (int l = 0; l <= L; ++l) {
+        out->M[l] = done[l];
+        out->Yhat[l] = Y[l];
+        out->Vhat[l] = V[l];
+        out->cost[l] = cost[l];
+        est += Y[l];
+        var += V[l] / (double)done[l];
+    }
+    out->estimate[0] = est;
+    out->var_est[0] = var;
+    out->L = L;
+    out->converged = conv ? 1 : 0;
+    out->rounds = rounds;
+    out->bias_est = bias_remainder(Y, L, o.alpha);
+    out->rmse_est = std::sqrt(var + out->bias_est * out->bias_est);
+    return conv ? DK_OK : DK_WARN_NOT_CONVERGED;
+}
+
+struct GpuSampler {
+    dk_context* ctx;
+    const dk_problem* p;
+    hipStream_t s;
+    uint32_t tag;
+    bool plain_mc;
+    std::vector<dk_moments> mom;   // [levels][n_obs]
+    std::vector<dk_moments> tmp;
+    double cell_updates = 0;
+};
+
+int gpu_sample(void* user, int32_t level, uint64_t first, uint64_t count, double* sums)
+{
+    GpuSampler& G = *(GpuSampler*)user;
+    const int nobs = G.p->n_obs;
+    G.tmp.assign(nobs, dk_moments{});
+    const bool pair = !G.plain_mc && level >= 1;
+    const int rc = run_level(G.ctx, G.p, level, pair, first, count, G.tag, G.tmp.data(), nullptr, nullptr, nullptr, G.s,
+                             &G.cell_updates);
+    if (rc < 0) return rc;
+    for (int j = 0; j < nobs; ++j) {
+        dk_moments& d = G.mom[(size_t)level * nobs + j];
+        d.count += G.tmp[j].count;
+        for (int k = 0; k < DK_NMOM; ++k) {
+            nadd(d.sum[k], d.comp[k], G.tmp[j].sum[k]);
+            d.comp[k] += G.tmp[j].comp[k];
+        }
+    }
+    const dk_moments& pm = G.tmp[G.p->primary_obs];
+    sums[0] = mom_value(pm, DK_MOM_Y);
+    sums[1] = mom_value(pm, DK_MOM_Y2);
+    return DK_OK;
+}
+
+double level_cost(const dk_problem* p, long steps0, int level, bool pair)
+{
+    const double n = (double)(p->n0 << level);
+    return n * n * (double)(steps0 << (2 * level)) * (pair && level >= 1 ? 1.0 + 1.0 / 16.0 : 1.0);
+}
+
+}  // namespace
+
+// ============================================================================================
+// C ABI
+// ============================================================================================
+extern "C" {
+
+const char* dk_last_error(void) { return g_err; }
+
+const char* dk_version(void) { return "dk_mlmc 0.1 (gfx950)"; }
+
+int dk_abi_sizes(int32_t* out, int32_t n)
+{
+    const int32_t sz[] = {(int32_t)sizeof(dk_mode), (int32_t)sizeof(dk_field), (int32_t)sizeof(dk_obs),
+                          (int32_t)sizeof(dk_problem), (int32_t)sizeof(dk_moments), (int32_t)sizeof(dk_mlmc_opts),
+                          (int32_t)sizeof(dk_mlmc_result)};
+    const int32_t k = (int32_t)(sizeof(sz) / sizeof(sz[0]));
+    for (int32_t i = 0; i < n && i < k; ++i) out[i] = sz[i];
+    return k;
+}
+
+int dk_context_create(dk_context** out, int device)
+{
+    if (!out) return fail(DK_EINVAL, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    HIP_TRY(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return fail(DK_EINVAL, "device %d outside [0, %d)", device, count);
+    HIP_TRY(hipSetDevice(device));
+    dk_context* c = new (std::nothrow) dk_context();
+    if (!c) return fail(DK_ENOMEM, "context allocation failed");
+    c->device = device;
+    *out = c;
+    return DK_OK;
+}
+
+void dk_context_destroy(dk_context* ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    delete ctx;
+}
+
+int dk_mlmc_level_pair(dk_context* ctx, const dk_problem* problem, int32_t level, uint64_t first_sample,
+                       uint64_t n_samples, uint32_t stream_tag, dk_moments* sums_out, double* per_sample_out, void* stream)
+{
+    if (!ctx) return fail(DK_EINVAL, "context is NULL");
+    if (!sums_out) return fail(DK_EINVAL, "sums_out is NULL");
+    if (stream_tag > 255) return fail(DK_EINVAL, "stream_tag must fit in 8 bits");
+    HIP_TRY(hipSetDevice(ctx->device));
+    return run_level(ctx, problem, level, level >= 1, first_sample, n_samples, stream_tag, sums_out, per_sample_out,
+                     nullptr, nullptr, (hipStream_t)stream, nullptr);
+}
+
+int dk_mc_level(dk_context* ctx, const dk_problem* problem, int32_t level, uint64_t first_sample, uint64_t n_samples,
+                dk_moments* sums_out, double* per_sample_out, void* stream)
+{
+    if (!ctx) return fail(DK_EINVAL, "context is NULL");
+    if (!sums_out) return fail(DK_EINVAL, "sums_out is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    return run_level(ctx, problem, level, false, first_sample, n_samples, DK_TAG_MC, sums_out, per_sample_out, nullptr,
+                     nullptr, (hipStream_t)stream, nullptr);
+}
+
+int dk_level_fields(dk_context* ctx, const dk_problem* problem, int32_t level, int32_t coupled, uint64_t first_sample,
+                    uint64_t n_samples, uint32_t stream_tag, double* per_sample_out, void* rho_f_out, void* rho_c_out,
+                    void* stream)
+{
+    if (!ctx) return fail(DK_EINVAL, "context is NULL");
+    if (!rho_f_out) return fail(DK_EINVAL, "rho_f_out is NULL");
+    if (coupled && !rho_c_out) return fail(DK_EINVAL, "rho_c_out is NULL");
+    if (stream_tag > 255) return fail(DK_EINVAL, "stream_tag must fit in 8 bits");
+    HIP_TRY(hipSetDevice(ctx->device));
+    if (!problem) return fail(DK_EINVAL, "problem is NULL");
+    std::vector<dk_moments> tmp(std::max(1, problem->n_obs));
+    return run_level(ctx, problem, level, coupled != 0, first_sample, n_samples, stream_tag, tmp.data(), per_sample_out,
+                     rho_f_out, rho_c_out, (hipStream_t)stream, nullptr);
+}
+
+int dk_meanfield(dk_context* ctx, const dk_problem* problem, int32_t level, double* centre_out, double* rho_out,
+                 void* stream)
+{
+    if (!ctx) return fail(DK_EINVAL, "context is NULL");
+    if (!centre_out) return fail(DK_EINVAL, "centre_out is NULL");
+    int rc = validate(problem);
+    if (rc) return rc;
+    if (level < 0 || level >= problem->levels) return fail(DK_EINVAL, "level out of range");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    // level tables (phi) without requiring centring
+    LevelTables* T = nullptr;
+    rc = ensure_level(ctx, problem, level, &T, s);
+    if (rc) return rc;
+    if (!T->have_centre || rho_out) {
+        rc = compute_centre(ctx, problem, level, *T, s, rho_out);
+        if (rc) return rc;
+    }
+    for (int j = 0; j < problem->n_obs; ++j) centre_out[j] = T->centre[j];
+    return DK_OK;
+}
+
+int dk_noise_dump(dk_context* ctx, uint64_t seed, uint32_t tag, int32_t level, int32_t n, uint64_t first_sample,
+                  uint32_t n_samples, int32_t first_step, int32_t n_steps, float* out, void* stream)
+{
+    if (!ctx) return fail(DK_EINVAL, "context is NULL");
+    if (!out) return fail(DK_EINVAL, "out is NULL");
+    if (n < 2 || (n & 1) || n > 4096) return fail(DK_EINVAL, "n = %d must be even in [2, 4096]", n);
+    if (tag > 255 || level < 0 || level > 255) return fail(DK_EINVAL, "tag and level must fit in 8 bits");
+    if (first_step < 0 || n_steps < 0) return fail(DK_EINVAL, "negative step range");
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(dk::launch_noise_dump(seed, tag, level, n, first_sample, n_samples, first_step, n_steps, out,
+                                  (hipStream_t)stream));
+    return DK_OK;
+}
+
+int dk_alg1_host(double eps, int32_t L_max, const double* cost, const dk_mlmc_opts* opts, dk_level_sampler sampler,
+                 void* user, dk_mlmc_result* out)
+{
+    if (!cost || !sampler || !out) return fail(DK_EINVAL, "NULL argument");
+    const dk_mlmc_opts o = opts ? *opts : default_opts();
+    return alg1_core(eps, L_max, cost, o, sampler, user, out);
+}
+
+int dk_mlmc_estimate(dk_context* ctx, const dk_problem* problem, double eps, const dk_mlmc_opts* opts,
+                     dk_mlmc_result* out, dk_moments* level_moments, void* stream)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!ctx) return fail(DK_EINVAL, "context is NULL");
+    if (!out) return fail(DK_EINVAL, "out is NULL");
+    int rc = validate(problem);
+    if (rc) return rc;
+    HIP_TRY(hipSetDevice(ctx->device));
+    dk_mlmc_opts o = opts ? *opts : default_opts();
+    if (o.m_pilot == 0) o.m_pilot = 1000;
+    if (o.alpha == 0) o.alpha = 2.0;
+    if (o.max_rounds == 0) o.max_rounds = 1000;
+    const long s0 = steps0_of(problem);
+    const int nobs = problem->n_obs;
+    GpuSampler G;
+    G.ctx = ctx;
+    G.p = problem;
+    G.s = (hipStream_t)stream;
+    G.mom.assign((size_t)problem->levels * nobs, dk_moments{});
+    const bool mc = o.plain_mc_level >= 0;
+    if (mc && o.plain_mc_level >= problem->levels) return fail(DK_EINVAL, "plain_mc_level out of range");
+    G.plain_mc = mc;
+    G.tag = mc ? DK_TAG_MC : DK_TAG_MLMC;
+    if (!mc) {
+        std::vector<double> cost(problem->levels);
+        for (int l = 0; l < problem->levels; ++l) cost[l] = level_cost(problem, s0, l, true);
+        rc = alg1_core(eps, problem->levels - 1, cost.data(), o, gpu_sample, &G, out);
+        if (rc < 0) return rc;
+    } else {
+        // plain MC on one level: pilot, then M = ceil(2 V / eps^2) so that V / M <= eps^2 / 2
+        const int l = o.plain_mc_level;
+        uint64_t done = 0, target = (uint64_t)o.m_pilot;
+        double s1 = 0, c1 = 0, s2 = 0, c2 = 0, mean = 0, var = 0;
+        int rounds = 0;
+        while (done < target) {
+            ++rounds;
+            double sums[2];
+            rc = gpu_sample(&G, l, done, target - done, sums);
+            if (rc < 0) return rc;
+            nadd(s1, c1, sums[0]);
+            nadd(s2, c2, sums[1]);
+            done = target;
+            mean = (s1 + c1) / (double)done;
+            var = std::max(0.0, ((s2 + c2) - (double)done * mean * mean) / ((double)done - 1.0));
+            uint64_t m = (uint64_t)std::ceil(2.0 * var / (eps * eps));
+            if (o.max_samples && m > o.max_samples) m = o.max_samples;
+            target = std::max(done, m);
+            if (rounds > o.max_rounds) return fail(DK_EINVAL, "plain MC exceeded max_rounds");
+        }
+        std::memset(out, 0, sizeof(*out));
+        out->L = l;
+        out->M[l] = done;
+        out->Yhat[l] = mean;
+        out->Vhat[l] = var;
+        out->cost[l] = level_cost(problem, s0, l, false);
+        out->estimate[0] = mean;
+        out->var_est[0] = var / (double)done;
+        out->rmse_est = std::sqrt(out->var_est[0]);
+        out->converged = 1;
+        out->rounds = rounds;
+        rc = DK_OK;
+    }
+    // all observables from the accumulated moments
+    for (int j = 0; j < nobs; ++j) {
+        double est = 0.0, var = 0.0;
+        for (int l = 0; l <= out->L; ++l) {
+            const dk_moments& m = G.mom[(size_t)l * nobs + j];
+            if (m.count == 0) continue;
+            const double n = (double)m.count;
+            const double y = mom_value(m, DK_MOM_Y) / n;
+            const double v = n > 1 ? std::max(0.0, (mom_value(m, DK_MOM_Y2) - n * y * y) / (n - 1.0)) : 0.0;
+            est += y;
+            var += v / n;
+        }
+        out->estimate[j] = est;
+        out->var_est[j] = var;
+    }
+    if (!mc) out->rmse_est = std::sqrt(out->var_est[problem->primary_obs] + out->bias_est * out->bias_est);
+    out->cell_updates = G.cell_updates;
+    if (level_moments) std::memcpy(level_moments, G.mom.data(), sizeof(dk_moments) * G.mom.size());
+    out->wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,119 @@
+// dk_rng.h -- device-side noise generator for gfx950.
+//
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32->64 products
+// of words 0 and 2 with the round multipliers, whose high halves are XORed with words 1, 3
+// and the round key; the key advances by the two Weyl increments between rounds.
+//
+// Gaussian transform (Box & Muller 1958) as a fixed sequence of correctly rounded binary32
+// operations, so its bits are reproducible on any IEEE-754 machine that performs the same
+// sequence (no contraction inside; every fused multiply-add is written explicitly):
+//   radius word a -> odd integer w = 2 (a >> 9) + 1, u = w 2^-24;
+//     w = 2^e m, m in [1, 2), folded into [sqrt(1/2), sqrt(2)];
+//     ln u = (e - 24) ln 2 + 2 atanh((m - 1)/(m + 1)), atanh by its odd power series to s^11;
+//     R = sqrt(-2 ln u)   (|R| <= sqrt(48 ln 2), a tail cut at probability ~1e-8)
+//   angle word b -> quadrant b >> 30 and fraction f = (2 ((b >> 7) & 0x7fffff) + 1) 2^-24;
+//     the angle inside the quadrant is reduced to at most pi/4 by the complement, and its
+//     sine and cosine come from their Taylor series to degree 11 and 12;
+//   (z0, z1) = R (cos, sin)(pi/2 (q + f)).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dk {
+
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        U4 n;
+        n.x = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
+        n.y = (uint32_t)p1;
+        n.z = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+        n.w = (uint32_t)p0;
+        c = n;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// 2^-e as a binary32 bit pattern (0 <= e <= 24)
+__device__ __forceinline__ float pow2_neg(int e) { return __int_as_float((127 - e) << 23); }
+
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, float& z1)
+{
+#pragma clang fp contract(off)
+    const uint32_t w = ((a >> 9) << 1) | 1u;
+    int e = 31 - __builtin_clz(w);
+    float m = (float)w * pow2_neg(e);
+    if (m > 1.41421356f) { m = m * 0.5f; e += 1; }
+    const float s = (m - 1.0f) / (m + 1.0f);   // correctly rounded (built with -fhip-fp32-correctly-rounded-divide-sqrt)
+    const float t = s * s;
+    float p = __builtin_fmaf(1.0f / 11.0f, t, 1.0f / 9.0f);
+    p = __builtin_fmaf(p, t, 1.0f / 7.0f);
+    p = __builtin_fmaf(p, t, 1.0f / 5.0f);
+    p = __builtin_fmaf(p, t, 1.0f / 3.0f);
+    p = p * t;
+    const float ath = __builtin_fmaf(s, p, s);
+    const float ne = (float)(e - 24);
+    const float hi = ne * 0x1.62ep-1f;
+    const float lo = __builtin_fmaf(ne, (float)(0.69314718055994530942 - 0.693115234375), 2.0f * ath);
+    const float R = __builtin_sqrtf(-2.0f * (hi + lo));   // correctly rounded, as the division
+
+    const uint32_t q = b >> 30;
+    const float f = (float)((((b >> 7) & 0x7FFFFFu) << 1) | 1u) * 0x1p-24f;
+    const bool flip = f > 0.5f;
+    const float g = flip ? 1.0f - f : f;
+    const float x = g * 0x1.921fb6p+0f;
+    const float x2 = x * x;
+    float ps = __builtin_fmaf(-1.0f / 39916800.0f, x2, 1.0f / 362880.0f);
+    ps = __builtin_fmaf(ps, x2, -1.0f / 5040.0f);
+    ps = __builtin_fmaf(ps, x2, 1.0f / 120.0f);
+    ps = __builtin_fmaf(ps, x2, -1.0f / 6.0f);
+    const float sn = __builtin_fmaf(x * x2, ps, x);
+    float pc = __builtin_fmaf(1.0f / 479001600.0f, x2, -1.0f / 3628800.0f);
+    pc = __builtin_fmaf(pc, x2, 1.0f / 40320.0f);
+    pc = __builtin_fmaf(pc, x2, -1.0f / 720.0f);
+    pc = __builtin_fmaf(pc, x2, 1.0f / 24.0f);
+    pc = __builtin_fmaf(pc, x2, -0.5f);
+    const float cs = __builtin_fmaf(x2, pc, 1.0f);
+    const float cq = flip ? sn : cs;
+    const float sq = flip ? cs : sn;
+    // rotate by q quarter turns: (c, s) -> (-s, c)
+    const float c1 = (q & 1u) ? -sq : cq;
+    const float s1 = (q & 1u) ? cq : sq;
+    const float c2 = (q & 2u) ? -c1 : c1;
+    const float s2 = (q & 2u) ? -s1 : s1;
+    z0 = R * c2;
+    z1 = R * s2;
+}
+
+// Normals of the horizontal site pair (2a, y), (2a+1, y) at fine step m.
+struct NoiseKey {
+    uint32_t k0, k1;     // seed
+    uint32_t c2, c3;     // sample bits and tag|level|sample_hi
+};
+
+__device__ __forceinline__ NoiseKey make_key(uint64_t seed, uint32_t tag, int level, uint64_t sample)
+{
+    NoiseKey k;
+    k.k0 = (uint32_t)seed;
+    k.k1 = (uint32_t)(seed >> 32);
+    k.c2 = (uint32_t)sample;
+    k.c3 = (tag << 24) | ((uint32_t)level << 16) | (uint32_t)((sample >> 32) & 0xFFFFu);
+    return k;
+}
+
+__device__ __forceinline__ void site_pair_normals(const NoiseKey& k, uint32_t pair_index, uint32_t step,
+                                                  float& a0, float& a1, float& b0, float& b1)
+{
+    const U4 o = philox10(U4{pair_index, step, k.c2, k.c3}, k.k0, k.k1);
+    box_muller(o.x, o.y, a0, a1);
+    box_muller(o.z, o.w, b0, b1);
+}
+
+}  // namespace dk
