@@ -74,6 +74,10 @@ extern "C" {
 
 #define DK_TAG_MLMC 0         /* noise stream tags */
 #define DK_TAG_MC 1
+#define DK_TAG_CV_TRAIN 2     /* training pairs of the control variate              */
+#define DK_TAG_CV_COARSE 3    /* independent coarse-only paths of the control variate */
+
+#define DK_CNN_NPARAM 5953    /* parameters of the control-variate network */
 
 #define DK_MAX_OBS 64
 #define DK_MAX_LEVELS 12
@@ -140,6 +144,9 @@ typedef struct {
     int32_t max_rounds;       /* safety cap on Algorithm-1 rounds (default 1000)                  */
     int32_t plain_mc_level;   /* >= 0: run plain MC on this level instead of MLMC                 */
     uint64_t max_samples;     /* cap on total samples of one level (0 = none)                     */
+    const float* cv_params;   /* host [levels][DK_CNN_NPARAM] network parameters, or NULL         */
+    uint32_t cv_level_mask;   /* bit l set: level l >= 1 uses the learned control variate         */
+    int32_t cv_ratio;         /* independent coarse-only paths per pair (default 4)               */
 } dk_mlmc_opts;
 
 typedef struct {
@@ -221,11 +228,66 @@ typedef int (*dk_level_sampler)(void* user, int32_t level, uint64_t first, uint6
 int dk_alg1_host(double eps, int32_t L_max, const double* cost, const dk_mlmc_opts* opts,
                  dk_level_sampler sampler, void* user, dk_mlmc_result* out);
 
+/* ---- learned control variate (an extension of the method; plain MLMC stays the fallback) ----
+ * For a level l >= 1 with network r (coarse final field -> prediction of Y_l), each MLMC sample
+ * of level l is Z = (Y_l - r(x_c)) + (1/k) sum_{j<k} r(x'_j) with x_c the pair's normalised coarse
+ * field and x'_j from k independent level-(l-1) paths (stream DK_TAG_CV_COARSE, sample indices
+ * k i + j).  E[Z] = E[Y_l] for any fixed r, so the estimator stays unbiased; its variance is
+ * Var(Y - r) + Var(r)/k.  Inputs are x = N^{1/2} h_c (rho_c^T - rho_bar_c^T).
+ * The network: conv3x3 1->16, 16->16, 16->16 (circular, ReLU), global mean, dense 16->64 (ReLU),
+ * dense 64->1; parameters flat FP32 in the order W1 b1 W2 b2 W3 b3 U1 c1 U2 c2 with conv weights
+ * [out][in][ky][kx] and dense weights [out][in].  The 16->16 layers run on BF16 MFMA with FP32
+ * accumulation; the rest in FP32. */
+
+/* Seeded He initialisation of the network parameters (host only). */
+int dk_cnn_init(uint64_t seed, float* params_out);
+
+/* r[b] = network(x[b]) for x DEVICE [batch][n][n] floats (n a multiple of 4), r DEVICE [batch]. */
+int dk_cnn_forward(dk_context* ctx, const float* params, int32_t n, int32_t batch, const float* x, float* r,
+                   void* stream);
+
+/* Mean squared error of the network on (x, y) (DEVICE [batch][n][n], [batch]) and its gradient
+ * with respect to the parameters (host [DK_CNN_NPARAM]). */
+int dk_cnn_loss_grad(dk_context* ctx, const float* params, int32_t n, int32_t batch, const float* x, const float* y,
+                     float* grad_out, double* loss_out, void* stream);
+
+/* Train the network for level `level` >= 1 with Adam on n_train coupled pairs drawn from the
+ * DK_TAG_CV_TRAIN stream (targets Y of the primary observable, standardised internally; the
+ * scaling is folded into the last layer).  params_inout: host [DK_CNN_NPARAM], the initial values
+ * on entry.  loss_hist: optional host [epochs] (mean squared error on the standardised targets).
+ * val_out: optional host [3] = {Var(Y), Var(Y - r), Var(r)} on n_val further training-stream
+ * pairs (0 = skip). */
+int dk_cv_train(dk_context* ctx, const dk_problem* problem, int32_t level, uint64_t n_train, int32_t epochs,
+                int32_t batch, double lr, uint64_t n_val, float* params_inout, double* loss_hist, double* val_out,
+                void* stream);
+
+/* Per-kernel timing of a context, measured with HIP events around every level-kernel launch
+ * on the caller's stream (for profiling and roofline reports).  One record per
+ * (level, coupled) pair that ran since the last reset. */
+typedef struct {
+    int32_t level;            /* fine level                                  */
+    int32_t coupled;          /* 1 for NN-coupled pairs                      */
+    uint64_t launches;        /* kernel launches                             */
+    uint64_t samples;         /* samples (or pairs) computed                 */
+    double kernel_ms;         /* summed event time of the launches           */
+    double cell_updates;      /* fine + coarse cell updates                  */
+} dk_kernel_stats;
+
+/* Copies up to max records into out and returns the number of records (>= 0). */
+int dk_context_stats(dk_context* ctx, dk_kernel_stats* out, int32_t max);
+/* Clears the records; also drops cached level tables when drop_tables != 0. */
+int dk_context_reset(dk_context* ctx, int32_t drop_tables);
+
 /* Description of the last error on the calling thread (static storage, never NULL). */
 const char* dk_last_error(void);
 
 /* Library version string. */
 const char* dk_version(void);
+
+/* sizeof of dk_mode, dk_field, dk_obs, dk_problem, dk_moments, dk_mlmc_opts, dk_mlmc_result,
+ * dk_kernel_stats (in that order) into out[0..n); returns the number of entries (bindings
+ * use it to check their struct layouts). */
+int dk_abi_sizes(int32_t* out, int32_t n);
 
 #ifdef __cplusplus
 }

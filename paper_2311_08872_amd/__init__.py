@@ -19,7 +19,7 @@ import dk_workloads as W
 from . import _lib as L
 
 __all__ = ["Context", "Moments", "level_pair", "mc_level", "estimate", "meanfield", "noise_dump",
-           "level_fields", "alg1_host", "DKError"]
+           "level_fields", "alg1_host", "cnn_init", "cnn_forward", "cnn_loss_grad", "cv_train", "DKError"]
 
 
 class DKError(RuntimeError):
@@ -122,6 +122,17 @@ class Context:
         except Exception:
             pass
 
+    def stats(self) -> list:
+        """Per (level, coupled) kernel timings recorded with HIP events since the last reset."""
+        n = _check(self.lib.dk_context_stats(self.h, None, 0))
+        arr = (L.dk_kernel_stats * max(n, 1))()
+        n = _check(self.lib.dk_context_stats(self.h, arr, n))
+        return [{"level": r.level, "coupled": bool(r.coupled), "launches": r.launches, "samples": r.samples,
+                 "kernel_ms": r.kernel_ms, "cell_updates": r.cell_updates} for r in arr[:n]]
+
+    def reset(self, drop_tables: bool = False):
+        _check(self.lib.dk_context_reset(self.h, int(drop_tables)))
+
     def stream(self):
         torch = _torch()
         return C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
@@ -174,8 +185,16 @@ def mc_level(problem, level: int, first: int, n: int, per_sample: bool = False, 
     return (_moments(sums), out) if per_sample else _moments(sums)
 
 
-def _opts(m_pilot=1000, L_start=2, alpha=2.0, max_rounds=1000, plain_mc_level=-1, max_samples=0):
-    return L.dk_mlmc_opts(m_pilot, L_start, alpha, max_rounds, plain_mc_level, max_samples)
+def _opts(m_pilot=1000, L_start=2, alpha=2.0, max_rounds=1000, plain_mc_level=-1, max_samples=0, cv_params=None,
+          cv_level_mask=0, cv_ratio=4, _keep=None):
+    ptr = None
+    if cv_params is not None:
+        arr = np.ascontiguousarray(cv_params, dtype=np.float32)
+        if _keep is not None:
+            _keep.append(arr)
+        ptr = arr.ctypes.data_as(C.POINTER(C.c_float))
+    return L.dk_mlmc_opts(m_pilot, L_start, alpha, max_rounds, plain_mc_level, max_samples, ptr, cv_level_mask,
+                          cv_ratio)
 
 
 def _result_dict(r: L.dk_mlmc_result, nobs: int, rc: int) -> dict:
@@ -192,7 +211,8 @@ def estimate(problem, eps: float, ctx: Context | None = None, level_moments: boo
     ctx = ctx or default_context()
     cp = _cp(problem)
     nobs = len(cp.p.obs)
-    o = _opts(**opts)
+    keep = []
+    o = _opts(_keep=keep, **opts)
     r = L.dk_mlmc_result()
     mom = (L.dk_moments * (cp.p.levels * nobs))() if level_moments else None
     rc = _check(ctx.lib.dk_mlmc_estimate(ctx.h, cp.ref, eps, C.byref(o), C.byref(r), mom, ctx.stream()))
@@ -245,6 +265,56 @@ def level_fields(problem, level: int, coupled: bool, first: int, n: int, tag: in
     _check(ctx.lib.dk_level_fields(ctx.h, cp.ref, level, int(coupled), first, n, tag, _ptr(ps), _ptr(rf), _ptr(rc),
                                    ctx.stream()))
     return ps, rf, rc
+
+
+def cnn_init(seed: int = 0) -> np.ndarray:
+    """dk_cnn_init: seeded He initialisation of the network parameters (float32 [5953])."""
+    lib = L.load()
+    out = np.zeros(L.DK_CNN_NPARAM, np.float32)
+    _check(lib.dk_cnn_init(seed, out.ctypes.data_as(C.POINTER(C.c_float))))
+    return out
+
+
+def _fptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def cnn_forward(params: np.ndarray, x, ctx: Context | None = None):
+    """dk_cnn_forward: x float32 device tensor [batch, n, n] -> float32 device tensor [batch]."""
+    ctx = ctx or default_context()
+    torch = _torch()
+    params = np.ascontiguousarray(params, dtype=np.float32)
+    x = x.contiguous()
+    r = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+    _check(ctx.lib.dk_cnn_forward(ctx.h, _fptr(params), x.shape[1], x.shape[0], _ptr(x), _ptr(r), ctx.stream()))
+    return r
+
+
+def cnn_loss_grad(params: np.ndarray, x, y, ctx: Context | None = None):
+    """dk_cnn_loss_grad: (mean squared error, gradient float32 [5953]) on device tensors x, y."""
+    ctx = ctx or default_context()
+    params = np.ascontiguousarray(params, dtype=np.float32)
+    x = x.contiguous()
+    y = y.contiguous()
+    g = np.zeros(L.DK_CNN_NPARAM, np.float32)
+    loss = C.c_double()
+    _check(ctx.lib.dk_cnn_loss_grad(ctx.h, _fptr(params), x.shape[1], x.shape[0], _ptr(x), _ptr(y), _fptr(g),
+                                    C.byref(loss), ctx.stream()))
+    return loss.value, g
+
+
+def cv_train(problem, level: int, n_train: int = 1 << 16, epochs: int = 10, batch: int = 256, lr: float = 1e-3,
+             n_val: int = 8192, params: np.ndarray | None = None, seed: int = 0, ctx: Context | None = None) -> dict:
+    """dk_cv_train: train the control-variate network of `level` on the GPU."""
+    ctx = ctx or default_context()
+    cp = _cp(problem)
+    prm = np.ascontiguousarray(cnn_init(seed) if params is None else params, dtype=np.float32).copy()
+    hist = np.zeros(epochs)
+    val = np.zeros(3)
+    _check(ctx.lib.dk_cv_train(ctx.h, cp.ref, level, n_train, epochs, batch, lr, n_val, _fptr(prm),
+                               hist.ctypes.data_as(C.POINTER(C.c_double)), val.ctypes.data_as(C.POINTER(C.c_double)),
+                               ctx.stream()))
+    return {"params": prm, "loss": hist.tolist(), "var_Y": val[0], "var_Y_minus_r": val[1], "var_r": val[2]}
 
 
 def alg1_host(eps: float, L_max: int, cost, sampler: Callable[[int, int, int], np.ndarray], **opts) -> dict:

@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(_HERE, "libdk_mlmc.so")
 DK_MAX_OBS = 64
 DK_MAX_LEVELS = 12
 DK_NMOM = 6
+DK_CNN_NPARAM = 5953
 
 
 class dk_mode(C.Structure):
@@ -42,7 +43,8 @@ class dk_moments(C.Structure):
 
 class dk_mlmc_opts(C.Structure):
     _fields_ = [("m_pilot", C.c_int32), ("L_start", C.c_int32), ("alpha", C.c_double), ("max_rounds", C.c_int32),
-                ("plain_mc_level", C.c_int32), ("max_samples", C.c_uint64)]
+                ("plain_mc_level", C.c_int32), ("max_samples", C.c_uint64), ("cv_params", C.POINTER(C.c_float)),
+                ("cv_level_mask", C.c_uint32), ("cv_ratio", C.c_int32)]
 
 
 class dk_mlmc_result(C.Structure):
@@ -51,6 +53,11 @@ class dk_mlmc_result(C.Structure):
                 ("rounds", C.c_int32), ("reserved", C.c_int32), ("M", C.c_uint64 * DK_MAX_LEVELS),
                 ("Yhat", C.c_double * DK_MAX_LEVELS), ("Vhat", C.c_double * DK_MAX_LEVELS),
                 ("cost", C.c_double * DK_MAX_LEVELS), ("cell_updates", C.c_double), ("wall_s", C.c_double)]
+
+
+class dk_kernel_stats(C.Structure):
+    _fields_ = [("level", C.c_int32), ("coupled", C.c_int32), ("launches", C.c_uint64), ("samples", C.c_uint64),
+                ("kernel_ms", C.c_double), ("cell_updates", C.c_double)]
 
 
 SAMPLER = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int32, C.c_uint64, C.c_uint64, C.POINTER(C.c_double))
@@ -73,8 +80,19 @@ SIGNATURES = {
                                   C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dk_alg1_host": (C.c_int, [C.c_double, C.c_int32, C.POINTER(C.c_double), C.POINTER(dk_mlmc_opts), SAMPLER,
                                C.c_void_p, C.POINTER(dk_mlmc_result)]),
+    "dk_cnn_init": (C.c_int, [C.c_uint64, C.POINTER(C.c_float)]),
+    "dk_cnn_forward": (C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                 C.c_void_p]),
+    "dk_cnn_loss_grad": (C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                   C.POINTER(C.c_float), C.POINTER(C.c_double), C.c_void_p]),
+    "dk_cv_train": (C.c_int, [C.c_void_p, C.POINTER(dk_problem), C.c_int32, C.c_uint64, C.c_int32, C.c_int32,
+                              C.c_double, C.c_uint64, C.POINTER(C.c_float), C.POINTER(C.c_double),
+                              C.POINTER(C.c_double), C.c_void_p]),
+    "dk_context_stats": (C.c_int, [C.c_void_p, C.POINTER(dk_kernel_stats), C.c_int32]),
+    "dk_context_reset": (C.c_int, [C.c_void_p, C.c_int32]),
     "dk_last_error": (C.c_char_p, []),
     "dk_version": (C.c_char_p, []),
+    "dk_abi_sizes": (C.c_int, [C.POINTER(C.c_int32), C.c_int32]),
 }
 
 _lib = None
@@ -93,11 +111,10 @@ def load():
         fn = getattr(L, name)
         fn.restype = res
         fn.argtypes = args
-    L.dk_abi_sizes.restype = C.c_int
-    L.dk_abi_sizes.argtypes = [C.POINTER(C.c_int32), C.c_int32]
     sizes = (C.c_int32 * 16)()
     k = L.dk_abi_sizes(sizes, 16)
-    mine = [C.sizeof(t) for t in (dk_mode, dk_field, dk_obs, dk_problem, dk_moments, dk_mlmc_opts, dk_mlmc_result)]
+    mine = [C.sizeof(t) for t in (dk_mode, dk_field, dk_obs, dk_problem, dk_moments, dk_mlmc_opts, dk_mlmc_result,
+                                  dk_kernel_stats)]
     if list(sizes[:k]) != mine:
         raise RuntimeError(f"ABI mismatch between include/dk_mlmc.h ({list(sizes[:k])}) and the binding ({mine})")
     _lib = L

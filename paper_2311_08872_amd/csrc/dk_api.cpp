@@ -7,13 +7,16 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
 #include <string>
 #include <vector>
 
+#include "dk_cnn.h"
 #include "dk_internal.h"
+#include <random>
 
 namespace {
 
@@ -179,6 +182,8 @@ struct LevelTables {
     DevBuf obs;       // double [n_obs][3] {scale, centre, psi}
     std::vector<double> centre;   // c_{l,j} (0 where not centred)
     bool have_centre = false;
+    DevBuf rbar;                  // FP64 discrete mean field at the final time [n*n]
+    bool have_rbar = false;
 };
 
 struct ProblemTables {
@@ -187,13 +192,24 @@ struct ProblemTables {
 
 }  // namespace
 
+struct KStat {
+    uint64_t launches = 0, samples = 0;
+    double ms = 0, cells = 0;
+};
+
 struct dk_context {
     int device = 0;
+    std::map<std::pair<int, int>, KStat> stats;
+    std::vector<hipEvent_t> ev_pool;
     DevBuf per_sample;     // chunk buffer of per-sample outputs
     DevBuf moments;        // [chunks][n_obs][DK_NMOM][2]
     DevBuf mf0, mf1;       // mean-field streaming buffers
     DevBuf scratch_c;      // inner products
     std::vector<double> host_mom;
+    // learned control variate
+    dk::cnn::Workspace cnn;
+    DevBuf cv_prm, cv_grad, cv_m, cv_v, cv_loss;
+    DevBuf cv_fields, cv_x, cv_r, cv_y, cv_ps, cv_ps2, cv_z, cv_fields2, cv_x2, cv_r2;
     std::map<uint64_t, std::unique_ptr<ProblemTables>> problems;
 };
 
@@ -309,11 +325,17 @@ int ensure_level(dk_context* ctx, const dk_problem* p, int level, LevelTables** 
 
 constexpr uint64_t kMaxChunk = 1ull << 22;
 constexpr size_t kChunkBytes = 256ull << 20;
+constexpr double kMaxCellsPerLaunch = 2e12;   // about 5 s of kernel time per launch
 
-uint64_t chunk_size(int n_obs)
+// Samples per launch: bounded by the per-sample output buffer and by the work of one launch
+// (long levels are split so that no launch runs for more than a few seconds).
+uint64_t chunk_size(int n_obs, double cells_per_sample)
 {
     uint64_t c = kChunkBytes / (16ull * n_obs);
-    return std::min<uint64_t>(c, kMaxChunk);
+    c = std::min<uint64_t>(c, kMaxChunk);
+    const double by_work = std::floor(kMaxCellsPerLaunch / std::max(cells_per_sample, 1.0));
+    if (by_work < (double)c) c = std::max<uint64_t>(256, (uint64_t)by_work);
+    return c;
 }
 
 // Run samples [first, first+count) of level `level` (coupled pair if `pair`), reduce the
@@ -341,7 +363,9 @@ int run_level(dk_context* ctx, const dk_problem* p, int level, bool pair, uint64
     const int nobs = p->n_obs;
     for (int j = 0; j < nobs; ++j) std::memset(&sums_out[j], 0, sizeof(dk_moments));
     if (count == 0) return DK_OK;
-    const uint64_t ch = chunk_size(nobs);
+    const double cells_per_sample = (double)nf * nf * (double)Tf->steps * (pair ? 1.0 + 1.0 / 16.0 : 1.0);
+    const uint64_t ch = chunk_size(nobs, cells_per_sample);
+    const bool log = std::getenv("DK_LOG") != nullptr;
     const uint64_t nchunks = (count + ch - 1) / ch;
     if (!per_sample_out) {
         rc = ctx->per_sample.ensure(sizeof(double) * 2 * nobs * std::min<uint64_t>(ch, count));
@@ -372,6 +396,11 @@ int run_level(dk_context* ctx, const dk_problem* p, int level, bool pair, uint64
     A.n_obs = nobs;
     dk::LevelKind K{p->precision, pair, p->flux, true};
     const size_t esize = p->precision == DK_PREC_F64 ? 8 : 4;
+    while (ctx->ev_pool.size() < 2 * nchunks) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        ctx->ev_pool.push_back(e);
+    }
     for (uint64_t k = 0; k < nchunks; ++k) {
         const uint64_t b = k * ch;
         const uint64_t c = std::min(ch, count - b);
@@ -380,13 +409,33 @@ int run_level(dk_context* ctx, const dk_problem* p, int level, bool pair, uint64
         A.out = per_sample_out ? per_sample_out + b * nobs * 2 : (double*)ctx->per_sample.p;
         A.field_f = field_f ? (char*)field_f + b * esize * nf * nf : nullptr;
         A.field_c = (field_c && pair) ? (char*)field_c + b * esize * (nf / 2) * (nf / 2) : nullptr;
+        HIP_TRY(hipEventRecord(ctx->ev_pool[2 * k], s));
         HIP_TRY(dk::launch_level(K, A, s));
+        HIP_TRY(hipEventRecord(ctx->ev_pool[2 * k + 1], s));
         HIP_TRY(dk::launch_moments(A.out, c, nobs, (double*)ctx->moments.p + k * mom_stride, s));
+        if (log && nchunks > 1) {
+            // progress of long levels (waits for this launch)
+            HIP_TRY(hipEventSynchronize(ctx->ev_pool[2 * k + 1]));
+            std::fprintf(stderr, "[dk] level %d%s launch %llu/%llu (%llu samples)\n", level, pair ? " pair" : "",
+                         (unsigned long long)(k + 1), (unsigned long long)nchunks, (unsigned long long)c);
+            std::fflush(stderr);
+        }
     }
     ctx->host_mom.resize(mom_stride * nchunks);
     HIP_TRY(hipMemcpyAsync(ctx->host_mom.data(), ctx->moments.p, sizeof(double) * mom_stride * nchunks,
                            hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    {
+        KStat& st = ctx->stats[std::make_pair(level, pair ? 1 : 0)];
+        for (uint64_t k = 0; k < nchunks; ++k) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, ctx->ev_pool[2 * k], ctx->ev_pool[2 * k + 1]));
+            st.ms += ms;
+        }
+        st.launches += nchunks;
+        st.samples += count;
+        st.cells += (double)nf * nf * (double)Tf->steps * (pair ? 1.0 + 1.0 / 16.0 : 1.0) * (double)count;
+    }
     for (uint64_t k = 0; k < nchunks; ++k) {
         const uint64_t c = std::min(ch, count - k * ch);
         for (int j = 0; j < nobs; ++j) merge_moments(sums_out[j], &ctx->host_mom[k * mom_stride + j * DK_NMOM * 2], c);
@@ -474,6 +523,12 @@ int alg1_core(double eps, int L_max, const double* cost, const dk_mlmc_opts& o, 
             done[l] += extra;
         }
         stats(L);
+        if (std::getenv("DK_LOG")) {
+            std::fprintf(stderr, "[dk] round %d L=%d", rounds, L);
+            for (int l = 0; l <= L; ++l) std::fprintf(stderr, " | l%d M=%llu Y=%.4g V=%.4g", l, (unsigned long long)done[l], Y[l], V[l]);
+            std::fprintf(stderr, "\n");
+            std::fflush(stderr);
+        }
         double acc = 0.0;
         for (int l = 0; l <= L; ++l) acc += std::sqrt(V[l] * cost[l]);
         for (int l = 0; l <= L; ++l) {
@@ -504,6 +559,113 @@ int alg1_core(double eps, int L_max, const double* cost, const dk_mlmc_opts& o, 
     return conv ? DK_OK : DK_WARN_NOT_CONVERGED;
 }
 
+// ------------------------------------------------------------------------------------------
+// Learned control variate
+// ------------------------------------------------------------------------------------------
+int ensure_rbar(dk_context* ctx, const dk_problem* p, int level, LevelTables** out, hipStream_t s)
+{
+    LevelTables* T = nullptr;
+    int rc = ensure_level(ctx, p, level, &T, s);
+    if (rc) return rc;
+    if (!T->have_rbar) {
+        rc = T->rbar.ensure(sizeof(double) * (size_t)T->n * T->n);
+        if (rc) return rc;
+        rc = compute_centre(ctx, p, level, *T, s, (double*)T->rbar.p);
+        if (rc) return rc;
+        T->have_rbar = true;
+    }
+    *out = T;
+    return DK_OK;
+}
+
+constexpr int kCnnBatch = 1024;   // inputs per network launch sequence
+
+// r[count] = network(x[count][n][n]) in batches of kCnnBatch
+int cnn_forward_batched(dk_context* ctx, const float* prm, int n, uint64_t count, const float* x, float* r, hipStream_t s)
+{
+    if (count == 0) return DK_OK;
+    HIP_TRY(ctx->cnn.reserve(n, kCnnBatch));
+    HIP_TRY(dk::cnn::pack(ctx->cnn, prm, s));
+    for (uint64_t b = 0; b < count; b += kCnnBatch) {
+        const int c = (int)std::min<uint64_t>(kCnnBatch, count - b);
+        HIP_TRY(dk::cnn::forward(ctx->cnn, prm, x + b * n * n, c, r + b, s));
+    }
+    return DK_OK;
+}
+
+// Control-variate samples of level l >= 1: Z_i = (Y_i - r(x_i)) + mean_j r(x'_{k i + j}).
+// sums_out [n_obs] receives the plain pair moments (all observables); zsum receives the
+// moments of Z in the Y slots.
+int run_cv_level(dk_context* ctx, const dk_problem* p, int level, uint64_t first, uint64_t count, const float* prm_host,
+                 int kappa, dk_moments* sums_out, dk_moments& zsum, hipStream_t s, double* cell_updates)
+{
+    const int nobs = p->n_obs;
+    const int nc = p->n0 << (level - 1);
+    const size_t nn = (size_t)nc * nc;
+    LevelTables* Tc = nullptr;
+    int rc = ensure_rbar(ctx, p, level - 1, &Tc, s);
+    if (rc) return rc;
+    const double scale = std::sqrt(p->N) * Tc->h;
+    const bool f64 = p->precision == DK_PREC_F64;
+    const size_t es = f64 ? 8 : 4;
+    // sub-batches bounded by the field buffers (pair fields + kappa coarse-only fields)
+    const uint64_t cap = std::max<uint64_t>(256, (uint64_t)((1ull << 30) / (nn * (es + 4) * (1 + kappa))));
+    rc = ctx->cv_prm.ensure(sizeof(float) * dk::cnn::NPARAM);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(ctx->cv_prm.p, prm_host, sizeof(float) * dk::cnn::NPARAM, hipMemcpyHostToDevice, s));
+    const uint64_t S = std::min(cap, count);
+    if ((rc = ctx->cv_fields.ensure(es * nn * S))) return rc;
+    if ((rc = ctx->cv_x.ensure(4 * nn * S))) return rc;
+    if ((rc = ctx->cv_r.ensure(4 * S))) return rc;
+    if ((rc = ctx->cv_ps.ensure(16 * (size_t)nobs * S))) return rc;
+    if ((rc = ctx->cv_fields2.ensure(es * nn * S * kappa))) return rc;
+    if ((rc = ctx->cv_x2.ensure(4 * nn * S * kappa))) return rc;
+    if ((rc = ctx->cv_r2.ensure(4 * S * kappa))) return rc;
+    if ((rc = ctx->cv_ps2.ensure(16 * (size_t)nobs * S * kappa))) return rc;
+    if ((rc = ctx->cv_z.ensure(16 * S))) return rc;
+    for (int j = 0; j < nobs; ++j) std::memset(&sums_out[j], 0, sizeof(dk_moments));
+    std::memset(&zsum, 0, sizeof(zsum));
+    std::vector<dk_moments> part(nobs), part2(nobs);
+    for (uint64_t b = 0; b < count; b += S) {
+        const uint64_t c = std::min(S, count - b);
+        rc = run_level(ctx, p, level, true, first + b, c, DK_TAG_MLMC, part.data(), (double*)ctx->cv_ps.p, nullptr,
+                       ctx->cv_fields.p, s, cell_updates);
+        if (rc < 0) return rc;
+        for (int j = 0; j < nobs; ++j) {
+            sums_out[j].count += part[j].count;
+            for (int k = 0; k < DK_NMOM; ++k) {
+                nadd(sums_out[j].sum[k], sums_out[j].comp[k], part[j].sum[k]);
+                sums_out[j].comp[k] += part[j].comp[k];
+            }
+        }
+        HIP_TRY(dk::cnn::normalize(ctx->cv_fields.p, f64, (const double*)Tc->rbar.p, (int)nn, nn * c, scale,
+                                   (float*)ctx->cv_x.p, s));
+        rc = cnn_forward_batched(ctx, (const float*)ctx->cv_prm.p, nc, c, (const float*)ctx->cv_x.p, (float*)ctx->cv_r.p, s);
+        if (rc) return rc;
+        // independent coarse-only paths k (first + b) .. k (first + b + c)
+        rc = run_level(ctx, p, level - 1, false, (first + b) * kappa, c * kappa, DK_TAG_CV_COARSE, part2.data(),
+                       (double*)ctx->cv_ps2.p, ctx->cv_fields2.p, nullptr, s, cell_updates);
+        if (rc < 0) return rc;
+        HIP_TRY(dk::cnn::normalize(ctx->cv_fields2.p, f64, (const double*)Tc->rbar.p, (int)nn, nn * c * kappa, scale,
+                                   (float*)ctx->cv_x2.p, s));
+        rc = cnn_forward_batched(ctx, (const float*)ctx->cv_prm.p, nc, c * kappa, (const float*)ctx->cv_x2.p,
+                                 (float*)ctx->cv_r2.p, s);
+        if (rc) return rc;
+        HIP_TRY(dk::cnn::combine_cv((const double*)ctx->cv_ps.p, nobs, p->primary_obs, (const float*)ctx->cv_r.p,
+                                    (const float*)ctx->cv_r2.p, kappa, (int)c, (double*)ctx->cv_z.p, s));
+        rc = ctx->moments.ensure(sizeof(double) * DK_NMOM * 2);
+        if (rc) return rc;
+        HIP_TRY(dk::launch_moments((const double*)ctx->cv_z.p, c, 1, (double*)ctx->moments.p, s));
+        double h[DK_NMOM * 2];
+        HIP_TRY(hipMemcpyAsync(h, ctx->moments.p, sizeof(h), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        merge_moments(zsum, h, c);
+    }
+    if (!std::isfinite(mom_value(zsum, DK_MOM_Y)) || !std::isfinite(mom_value(zsum, DK_MOM_Y2)))
+        return fail(DK_ENUMERIC, "non-finite control-variate samples on level %d", level);
+    return DK_OK;
+}
+
 struct GpuSampler {
     dk_context* ctx;
     const dk_problem* p;
@@ -513,6 +675,10 @@ struct GpuSampler {
     std::vector<dk_moments> mom;   // [levels][n_obs]
     std::vector<dk_moments> tmp;
     double cell_updates = 0;
+    const float* cv_params = nullptr;   // [levels][NPARAM]
+    uint32_t cv_mask = 0;
+    int cv_ratio = 4;
+    std::vector<dk_moments> zmom;       // [levels] moments of the control-variate samples
 };
 
 int gpu_sample(void* user, int32_t level, uint64_t first, uint64_t count, double* sums)
@@ -521,9 +687,23 @@ int gpu_sample(void* user, int32_t level, uint64_t first, uint64_t count, double
     const int nobs = G.p->n_obs;
     G.tmp.assign(nobs, dk_moments{});
     const bool pair = !G.plain_mc && level >= 1;
-    const int rc = run_level(G.ctx, G.p, level, pair, first, count, G.tag, G.tmp.data(), nullptr, nullptr, nullptr, G.s,
-                             &G.cell_updates);
+    const bool cv = pair && G.cv_params && ((G.cv_mask >> level) & 1u);
+    dk_moments z{};
+    const int rc = cv ? run_cv_level(G.ctx, G.p, level, first, count, G.cv_params + (size_t)level * dk::cnn::NPARAM,
+                                     G.cv_ratio, G.tmp.data(), z, G.s, &G.cell_updates)
+                      : run_level(G.ctx, G.p, level, pair, first, count, G.tag, G.tmp.data(), nullptr, nullptr, nullptr,
+                                  G.s, &G.cell_updates);
     if (rc < 0) return rc;
+    if (cv) {
+        dk_moments& d = G.zmom[level];
+        d.count += z.count;
+        for (int k = 0; k < DK_NMOM; ++k) {
+            nadd(d.sum[k], d.comp[k], z.sum[k]);
+            d.comp[k] += z.comp[k];
+        }
+        sums[0] = mom_value(z, DK_MOM_Y);
+        sums[1] = mom_value(z, DK_MOM_Y2);
+    }
     for (int j = 0; j < nobs; ++j) {
         dk_moments& d = G.mom[(size_t)level * nobs + j];
         d.count += G.tmp[j].count;
@@ -532,11 +712,14 @@ int gpu_sample(void* user, int32_t level, uint64_t first, uint64_t count, double
             d.comp[k] += G.tmp[j].comp[k];
         }
     }
-    const dk_moments& pm = G.tmp[G.p->primary_obs];
-    sums[0] = mom_value(pm, DK_MOM_Y);
-    sums[1] = mom_value(pm, DK_MOM_Y2);
+    if (!cv) {
+        const dk_moments& pm = G.tmp[G.p->primary_obs];
+        sums[0] = mom_value(pm, DK_MOM_Y);
+        sums[1] = mom_value(pm, DK_MOM_Y2);
+    }
     return DK_OK;
 }
+
 
 double level_cost(const dk_problem* p, long steps0, int level, bool pair)
 {
@@ -555,11 +738,183 @@ const char* dk_last_error(void) { return g_err; }
 
 const char* dk_version(void) { return "dk_mlmc 0.1 (gfx950)"; }
 
+
+int dk_cnn_init(uint64_t seed, float* params_out)
+{
+    if (!params_out) return fail(DK_EINVAL, "params_out is NULL");
+    std::mt19937_64 gen(seed);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    using namespace dk::cnn;
+    auto he = [&](int off, int count, int fan_in) {
+        const double sd = std::sqrt(2.0 / fan_in);
+        for (int k = 0; k < count; ++k) params_out[off + k] = (float)(sd * nd(gen));
+    };
+    for (int k = 0; k < NPARAM; ++k) params_out[k] = 0.f;
+    he(OFF_W1, 144, 9);
+    he(OFF_W2, 2304, 144);
+    he(OFF_W3, 2304, 144);
+    he(OFF_U1, 1024, 16);
+    he(OFF_U2, 64, 64);
+    return DK_OK;
+}
+
+int dk_cnn_forward(dk_context* ctx, const float* params, int32_t n, int32_t batch, const float* x, float* r, void* stream)
+{
+    if (!ctx || !params || !x || !r) return fail(DK_EINVAL, "NULL argument");
+    if (n < 4 || n % 4 || n > 1024 || batch < 0) return fail(DK_EINVAL, "n must be a multiple of 4 in [4, 1024]");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    int rc = ctx->cv_prm.ensure(sizeof(float) * dk::cnn::NPARAM);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(ctx->cv_prm.p, params, sizeof(float) * dk::cnn::NPARAM, hipMemcpyHostToDevice, s));
+    rc = cnn_forward_batched(ctx, (const float*)ctx->cv_prm.p, n, (uint64_t)batch, x, r, s);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(s));
+    return DK_OK;
+}
+
+int dk_cnn_loss_grad(dk_context* ctx, const float* params, int32_t n, int32_t batch, const float* x, const float* y,
+                     float* grad_out, double* loss_out, void* stream)
+{
+    if (!ctx || !params || !x || !y || !grad_out) return fail(DK_EINVAL, "NULL argument");
+    if (n < 4 || n % 4 || n > 1024 || batch < 1) return fail(DK_EINVAL, "n must be a multiple of 4 in [4, 1024]");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    int rc;
+    if ((rc = ctx->cv_prm.ensure(sizeof(float) * dk::cnn::NPARAM))) return rc;
+    if ((rc = ctx->cv_grad.ensure(sizeof(float) * dk::cnn::NPARAM))) return rc;
+    if ((rc = ctx->cv_r.ensure(sizeof(float) * batch))) return rc;
+    if ((rc = ctx->cv_loss.ensure(sizeof(double)))) return rc;
+    HIP_TRY(hipMemcpyAsync(ctx->cv_prm.p, params, sizeof(float) * dk::cnn::NPARAM, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(ctx->cv_loss.p, 0, sizeof(double), s));
+    HIP_TRY(ctx->cnn.reserve(n, batch));
+    HIP_TRY(dk::cnn::pack(ctx->cnn, (const float*)ctx->cv_prm.p, s));
+    HIP_TRY(dk::cnn::forward(ctx->cnn, (const float*)ctx->cv_prm.p, x, batch, (float*)ctx->cv_r.p, s));
+    HIP_TRY(dk::cnn::backward(ctx->cnn, (const float*)ctx->cv_prm.p, x, (const float*)ctx->cv_r.p, y, batch,
+                              (float*)ctx->cv_grad.p, s));
+    HIP_TRY(dk::cnn::accumulate_sq(ctx->cnn, batch, (double*)ctx->cv_loss.p, s));
+    HIP_TRY(hipMemcpyAsync(grad_out, ctx->cv_grad.p, sizeof(float) * dk::cnn::NPARAM, hipMemcpyDeviceToHost, s));
+    double l = 0;
+    HIP_TRY(hipMemcpyAsync(&l, ctx->cv_loss.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (loss_out) *loss_out = l / batch;
+    return DK_OK;
+}
+
+int dk_cv_train(dk_context* ctx, const dk_problem* problem, int32_t level, uint64_t n_train, int32_t epochs,
+                int32_t batch, double lr, uint64_t n_val, float* params_inout, double* loss_hist, double* val_out,
+                void* stream)
+{
+    if (!ctx || !params_inout) return fail(DK_EINVAL, "NULL argument");
+    int rc = validate(problem);
+    if (rc) return rc;
+    if (level < 1 || level >= problem->levels) return fail(DK_EINVAL, "control variate needs 1 <= level < levels");
+    if (epochs < 1 || batch < 1 || n_train < (uint64_t)batch) return fail(DK_EINVAL, "need epochs >= 1 and n_train >= batch >= 1");
+    if (!(lr > 0)) return fail(DK_EINVAL, "lr must be > 0");
+    const int nc = problem->n0 << (level - 1);
+    if (nc % 4) return fail(DK_EINVAL, "coarse grid must be a multiple of 4");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int nobs = problem->n_obs;
+    const size_t nn = (size_t)nc * nc;
+    const bool f64 = problem->precision == DK_PREC_F64;
+    const size_t es = f64 ? 8 : 4;
+    LevelTables* Tc = nullptr;
+    if ((rc = ensure_rbar(ctx, problem, level - 1, &Tc, s))) return rc;
+    const double scale = std::sqrt(problem->N) * Tc->h;
+    const uint64_t ntot = n_train + n_val;
+    // training (and validation) pairs from the DK_TAG_CV_TRAIN stream
+    DevBuf fields, X, Y, PS;
+    if ((rc = fields.ensure(es * nn * ntot))) return rc;
+    if ((rc = X.ensure(4 * nn * ntot))) return rc;
+    if ((rc = Y.ensure(4 * ntot))) return rc;
+    if ((rc = PS.ensure(16 * (size_t)nobs * ntot))) return rc;
+    std::vector<dk_moments> mom(nobs);
+    rc = run_level(ctx, problem, level, true, 0, ntot, DK_TAG_CV_TRAIN, mom.data(), (double*)PS.p, nullptr, fields.p, s,
+                   nullptr);
+    if (rc < 0) return rc;
+    HIP_TRY(dk::cnn::normalize(fields.p, f64, (const double*)Tc->rbar.p, (int)nn, nn * ntot, scale, (float*)X.p, s));
+    HIP_TRY(dk::cnn::extract_y((const double*)PS.p, nobs, problem->primary_obs, (int)ntot, (float*)Y.p, s));
+    // standardise the targets (training part); the scaling is folded back into the last layer
+    std::vector<float> yh(ntot);
+    HIP_TRY(hipMemcpyAsync(yh.data(), Y.p, 4 * ntot, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double ym = 0, yv = 0;
+    for (uint64_t i = 0; i < n_train; ++i) ym += yh[i];
+    ym /= (double)n_train;
+    for (uint64_t i = 0; i < n_train; ++i) yv += (yh[i] - ym) * (yh[i] - ym);
+    const double ysd = std::sqrt(std::max(yv / std::max<double>(1.0, (double)n_train - 1), 1e-300));
+    std::vector<float> ys(n_train);
+    for (uint64_t i = 0; i < n_train; ++i) ys[i] = (float)((yh[i] - ym) / ysd);
+    DevBuf YS;
+    if ((rc = YS.ensure(4 * n_train))) return rc;
+    HIP_TRY(hipMemcpyAsync(YS.p, ys.data(), 4 * n_train, hipMemcpyHostToDevice, s));
+    using namespace dk::cnn;
+    if ((rc = ctx->cv_prm.ensure(4 * NPARAM))) return rc;
+    if ((rc = ctx->cv_grad.ensure(4 * NPARAM))) return rc;
+    if ((rc = ctx->cv_m.ensure(4 * NPARAM))) return rc;
+    if ((rc = ctx->cv_v.ensure(4 * NPARAM))) return rc;
+    if ((rc = ctx->cv_r.ensure(4 * (size_t)batch))) return rc;
+    if ((rc = ctx->cv_loss.ensure(sizeof(double) * epochs))) return rc;
+    HIP_TRY(hipMemcpyAsync(ctx->cv_prm.p, params_inout, 4 * NPARAM, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(ctx->cv_m.p, 0, 4 * NPARAM, s));
+    HIP_TRY(hipMemsetAsync(ctx->cv_v.p, 0, 4 * NPARAM, s));
+    HIP_TRY(hipMemsetAsync(ctx->cv_loss.p, 0, sizeof(double) * epochs, s));
+    HIP_TRY(ctx->cnn.reserve(nc, batch));
+    const uint64_t steps_per_epoch = n_train / (uint64_t)batch;
+    int t = 0;
+    for (int e = 0; e < epochs; ++e) {
+        for (uint64_t k = 0; k < steps_per_epoch; ++k) {
+            const float* xb = (const float*)X.p + k * batch * nn;
+            const float* yb = (const float*)YS.p + k * batch;
+            HIP_TRY(pack(ctx->cnn, (const float*)ctx->cv_prm.p, s));
+            HIP_TRY(forward(ctx->cnn, (const float*)ctx->cv_prm.p, xb, batch, (float*)ctx->cv_r.p, s));
+            HIP_TRY(backward(ctx->cnn, (const float*)ctx->cv_prm.p, xb, (const float*)ctx->cv_r.p, yb, batch,
+                             (float*)ctx->cv_grad.p, s));
+            HIP_TRY(accumulate_sq(ctx->cnn, batch, (double*)ctx->cv_loss.p + e, s));
+            HIP_TRY(adam_update((float*)ctx->cv_prm.p, (const float*)ctx->cv_grad.p, (float*)ctx->cv_m.p,
+                                (float*)ctx->cv_v.p, (float)lr, ++t, s));
+        }
+    }
+    std::vector<double> lh(epochs);
+    HIP_TRY(hipMemcpyAsync(lh.data(), ctx->cv_loss.p, sizeof(double) * epochs, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(params_inout, ctx->cv_prm.p, 4 * NPARAM, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (loss_hist)
+        for (int e = 0; e < epochs; ++e) loss_hist[e] = lh[e] / (double)(steps_per_epoch * batch);
+    // fold the target scaling into the last layer: r = ysd * r_std + ym
+    for (int k = 0; k < 64; ++k) params_inout[OFF_U2 + k] = (float)(ysd * params_inout[OFF_U2 + k]);
+    params_inout[OFF_C2] = (float)(ysd * params_inout[OFF_C2] + ym);
+    if (val_out && n_val > 0) {
+        HIP_TRY(hipMemcpyAsync(ctx->cv_prm.p, params_inout, 4 * NPARAM, hipMemcpyHostToDevice, s));
+        DevBuf RV;
+        if ((rc = RV.ensure(4 * n_val))) return rc;
+        rc = cnn_forward_batched(ctx, (const float*)ctx->cv_prm.p, nc, n_val, (const float*)X.p + n_train * nn,
+                                 (float*)RV.p, s);
+        if (rc) return rc;
+        std::vector<float> rv(n_val);
+        HIP_TRY(hipMemcpyAsync(rv.data(), RV.p, 4 * n_val, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        double my = 0, md = 0, mr = 0;
+        for (uint64_t i = 0; i < n_val; ++i) { my += yh[n_train + i]; md += yh[n_train + i] - rv[i]; mr += rv[i]; }
+        my /= n_val; md /= n_val; mr /= n_val;
+        double vy = 0, vd = 0, vr = 0;
+        for (uint64_t i = 0; i < n_val; ++i) {
+            const double a = yh[n_train + i] - my, b = (yh[n_train + i] - rv[i]) - md, c = rv[i] - mr;
+            vy += a * a; vd += b * b; vr += c * c;
+        }
+        val_out[0] = vy / (n_val - 1.0);
+        val_out[1] = vd / (n_val - 1.0);
+        val_out[2] = vr / (n_val - 1.0);
+    }
+    return DK_OK;
+}
+
 int dk_abi_sizes(int32_t* out, int32_t n)
 {
     const int32_t sz[] = {(int32_t)sizeof(dk_mode), (int32_t)sizeof(dk_field), (int32_t)sizeof(dk_obs),
                           (int32_t)sizeof(dk_problem), (int32_t)sizeof(dk_moments), (int32_t)sizeof(dk_mlmc_opts),
-                          (int32_t)sizeof(dk_mlmc_result)};
+                          (int32_t)sizeof(dk_mlmc_result), (int32_t)sizeof(dk_kernel_stats)};
     const int32_t k = (int32_t)(sizeof(sz) / sizeof(sz[0]));
     for (int32_t i = 0; i < n && i < k; ++i) out[i] = sz[i];
     return k;
@@ -584,7 +939,35 @@ void dk_context_destroy(dk_context* ctx)
 {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
+}
+
+int dk_context_stats(dk_context* ctx, dk_kernel_stats* out, int32_t max)
+{
+    if (!ctx) return fail(DK_EINVAL, "context is NULL");
+    int k = 0;
+    for (const auto& kv : ctx->stats) {
+        if (out && k < max) {
+            dk_kernel_stats& r = out[k];
+            r.level = kv.first.first;
+            r.coupled = kv.first.second;
+            r.launches = kv.second.launches;
+            r.samples = kv.second.samples;
+            r.kernel_ms = kv.second.ms;
+            r.cell_updates = kv.second.cells;
+        }
+        ++k;
+    }
+    return k;
+}
+
+int dk_context_reset(dk_context* ctx, int32_t drop_tables)
+{
+    if (!ctx) return fail(DK_EINVAL, "context is NULL");
+    ctx->stats.clear();
+    if (drop_tables) ctx->problems.clear();
+    return DK_OK;
 }
 
 int dk_mlmc_level_pair(dk_context* ctx, const dk_problem* problem, int32_t level, uint64_t first_sample,
@@ -691,9 +1074,23 @@ int dk_mlmc_estimate(dk_context* ctx, const dk_problem* problem, double eps, con
     if (mc && o.plain_mc_level >= problem->levels) return fail(DK_EINVAL, "plain_mc_level out of range");
     G.plain_mc = mc;
     G.tag = mc ? DK_TAG_MC : DK_TAG_MLMC;
+    G.zmom.assign(problem->levels, dk_moments{});
+    if (o.cv_params && !mc) {
+        G.cv_params = o.cv_params;
+        G.cv_mask = o.cv_level_mask & ~1u;
+        G.cv_ratio = o.cv_ratio > 0 ? o.cv_ratio : 4;
+        for (int l = 1; l < problem->levels; ++l)
+            if ((G.cv_mask >> l) & 1u) {
+                const int nc = problem->n0 << (l - 1);
+                if (nc % 4) return fail(DK_EINVAL, "control variate on level %d: coarse grid must be a multiple of 4", l);
+            }
+    }
     if (!mc) {
         std::vector<double> cost(problem->levels);
-        for (int l = 0; l < problem->levels; ++l) cost[l] = level_cost(problem, s0, l, true);
+        for (int l = 0; l < problem->levels; ++l) {
+            cost[l] = level_cost(problem, s0, l, true);
+            if ((G.cv_mask >> l) & 1u) cost[l] += G.cv_ratio * level_cost(problem, s0, l - 1, false);
+        }
         rc = alg1_core(eps, problem->levels - 1, cost.data(), o, gpu_sample, &G, out);
         if (rc < 0) return rc;
     } else {
@@ -734,7 +1131,8 @@ int dk_mlmc_estimate(dk_context* ctx, const dk_problem* problem, double eps, con
     for (int j = 0; j < nobs; ++j) {
         double est = 0.0, var = 0.0;
         for (int l = 0; l <= out->L; ++l) {
-            const dk_moments& m = G.mom[(size_t)l * nobs + j];
+            const bool cvl = j == problem->primary_obs && ((G.cv_mask >> l) & 1u) && G.zmom[l].count > 0;
+            const dk_moments& m = cvl ? G.zmom[l] : G.mom[(size_t)l * nobs + j];
             if (m.count == 0) continue;
             const double n = (double)m.count;
             const double y = mom_value(m, DK_MOM_Y) / n;
