@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--warmup-eps", type=float, default=1e-2, help="accuracy of the untimed warmup runs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle sampling")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 256 MiB buffer 4 times (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -99,6 +101,14 @@ def main():
     import paper_2311_08872_amd as dk
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_per_launch": 2 * src.numel() * 4, "launches": 4}), flush=True)
+        return
     base = W.config2(N=1e4)
 
     os.environ.setdefault("DK_LOG", "1")     # progress lines on stderr (per round and per long launch)
