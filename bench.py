@@ -136,6 +136,7 @@ def main():
             acc = stats.setdefault(key, {"launches": 0, "samples": 0, "kernel_ms": 0.0, "cell_updates": 0.0})
             for f in acc:
                 acc[f] += s[f]
+            acc["rows"] = s["rows"]
         ctx.close()
         results.append(r)
     torch.cuda.synchronize()

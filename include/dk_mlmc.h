@@ -271,12 +271,23 @@ typedef struct {
     uint64_t samples;         /* samples (or pairs) computed                 */
     double kernel_ms;         /* summed event time of the launches           */
     double cell_updates;      /* fine + coarse cell updates                  */
+    int32_t rows;             /* rows per lane of the tile shape used         */
+    int32_t reserved;
 } dk_kernel_stats;
 
 /* Copies up to max records into out and returns the number of records (>= 0). */
 int dk_context_stats(dk_context* ctx, dk_kernel_stats* out, int32_t max);
-/* Clears the records; also drops cached level tables when drop_tables != 0. */
+/* Clears the records; also drops cached level tables and tuning choices when drop_tables != 0. */
 int dk_context_reset(dk_context* ctx, int32_t drop_tables);
+
+/* Tile shapes of the resident kernel: a lane owns 2 columns and R rows of an n x n grid.
+ * dk_shape_rows(n, v) gives R of variant v (0 if the variant does not exist).  By default the
+ * context times the variants on a short batch the first time a large job (>= 1e11 cell updates)
+ * runs a grid size, and keeps the fastest; dk_context_set_shape forces variant v for grid size
+ * n (v < 0 restores the automatic choice).  Per-sample fields do not depend on the shape; the
+ * observables' FP64 lane reduction order does (last-bit differences). */
+int dk_context_set_shape(dk_context* ctx, int32_t n, int32_t variant);
+int dk_shape_rows(int32_t n, int32_t variant);
 
 /* Description of the last error on the calling thread (static storage, never NULL). */
 const char* dk_last_error(void);

@@ -128,7 +128,15 @@ class Context:
         arr = (L.dk_kernel_stats * max(n, 1))()
         n = _check(self.lib.dk_context_stats(self.h, arr, n))
         return [{"level": r.level, "coupled": bool(r.coupled), "launches": r.launches, "samples": r.samples,
-                 "kernel_ms": r.kernel_ms, "cell_updates": r.cell_updates} for r in arr[:n]]
+                 "kernel_ms": r.kernel_ms, "cell_updates": r.cell_updates, "rows": r.rows} for r in arr[:n]]
+
+    def set_shape(self, n: int, variant: int):
+        """Force tile-shape variant `variant` for grid size n (-1: automatic)."""
+        _check(self.lib.dk_context_set_shape(self.h, n, variant))
+
+    @staticmethod
+    def shape_rows(n: int, variant: int) -> int:
+        return L.load().dk_shape_rows(n, variant)
 
     def reset(self, drop_tables: bool = False):
         _check(self.lib.dk_context_reset(self.h, int(drop_tables)))

@@ -57,7 +57,7 @@ class dk_mlmc_result(C.Structure):
 
 class dk_kernel_stats(C.Structure):
     _fields_ = [("level", C.c_int32), ("coupled", C.c_int32), ("launches", C.c_uint64), ("samples", C.c_uint64),
-                ("kernel_ms", C.c_double), ("cell_updates", C.c_double)]
+                ("kernel_ms", C.c_double), ("cell_updates", C.c_double), ("rows", C.c_int32), ("reserved", C.c_int32)]
 
 
 SAMPLER = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int32, C.c_uint64, C.c_uint64, C.POINTER(C.c_double))
@@ -90,6 +90,8 @@ SIGNATURES = {
                               C.POINTER(C.c_double), C.c_void_p]),
     "dk_context_stats": (C.c_int, [C.c_void_p, C.POINTER(dk_kernel_stats), C.c_int32]),
     "dk_context_reset": (C.c_int, [C.c_void_p, C.c_int32]),
+    "dk_context_set_shape": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "dk_shape_rows": (C.c_int, [C.c_int32, C.c_int32]),
     "dk_last_error": (C.c_char_p, []),
     "dk_version": (C.c_char_p, []),
     "dk_abi_sizes": (C.c_int, [C.POINTER(C.c_int32), C.c_int32]),

@@ -195,11 +195,15 @@ struct ProblemTables {
 struct KStat {
     uint64_t launches = 0, samples = 0;
     double ms = 0, cells = 0;
+    int rows = 0;
 };
 
 struct dk_context {
     int device = 0;
     std::map<std::pair<int, int>, KStat> stats;
+    std::map<int, int> forced_shape;          // grid size -> tile-shape variant
+    std::map<long, int> tuned;                // (nf, pair, flux) -> variant chosen by timing
+    std::vector<std::pair<int, double>> tune_log;   // (variant, ms) of the last tuning
     std::vector<hipEvent_t> ev_pool;
     DevBuf per_sample;     // chunk buffer of per-sample outputs
     DevBuf moments;        // [chunks][n_obs][DK_NMOM][2]
@@ -338,6 +342,68 @@ uint64_t chunk_size(int n_obs, double cells_per_sample)
     return c;
 }
 
+// Tile-shape choice for the FP32 noisy kernels: a forced variant, a cached choice, or the
+// fastest variant on a short tuning batch (same tables, at most 256 fine steps, samples from
+// the requested range; the outputs are discarded).  Small jobs use the default shape.
+int choose_shape(dk_context* ctx, const dk_problem* p, bool pair, const dk::LevelArgs& A, uint64_t count,
+                 double cells_per_sample, hipStream_t s, int* variant)
+{
+    *variant = 0;
+    const int nf = A.nf;
+    auto f = ctx->forced_shape.find(nf);
+    if (f != ctx->forced_shape.end() && f->second >= 0) {
+        if (dk::shape_rows(nf, f->second) == 0) return fail(DK_EINVAL, "no tile-shape variant %d for n = %d", f->second, nf);
+        *variant = f->second;
+        return DK_OK;
+    }
+    if (p->precision != DK_PREC_F32) return DK_OK;
+    const long key = ((long)nf << 8) | ((long)pair << 4) | (long)p->flux;
+    auto t = ctx->tuned.find(key);
+    if (t != ctx->tuned.end()) { *variant = t->second; return DK_OK; }
+    if ((double)count * cells_per_sample < 1e11) return DK_OK;
+    int nvar = 0;
+    while (dk::shape_rows(nf, nvar) > 0) ++nvar;
+    if (nvar < 2) { ctx->tuned[key] = 0; return DK_OK; }
+    dk::LevelArgs T = A;
+    T.count = std::min<uint64_t>(count, nf <= 32 ? 8192 : (nf == 64 ? 2048 : 1024));
+    T.steps = std::min(A.steps, 256);
+    T.field_f = nullptr;
+    T.field_c = nullptr;
+    int rc = ctx->per_sample.ensure(sizeof(double) * 2 * A.n_obs * T.count);
+    if (rc) return rc;
+    T.out = (double*)ctx->per_sample.p;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    ctx->tune_log.clear();
+    double best = 1e300;
+    int bestv = 0;
+    for (int v = 0; v < nvar; ++v) {
+        dk::LevelKind K{p->precision, pair, p->flux, true, v};
+        HIP_TRY(dk::launch_level(K, T, s));   // warm-up
+        HIP_TRY(hipEventRecord(e0, s));
+        HIP_TRY(dk::launch_level(K, T, s));
+        HIP_TRY(dk::launch_level(K, T, s));
+        HIP_TRY(hipEventRecord(e1, s));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        ctx->tune_log.push_back(std::make_pair(v, (double)ms));
+        if (ms < best) { best = ms; bestv = v; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->tuned[key] = bestv;
+    if (std::getenv("DK_LOG")) {
+        std::fprintf(stderr, "[dk] tuned n=%d pair=%d flux=%d:", nf, (int)pair, p->flux);
+        for (auto& kv : ctx->tune_log) std::fprintf(stderr, " R=%d %.3f ms", dk::shape_rows(nf, kv.first), kv.second);
+        std::fprintf(stderr, " -> R=%d\n", dk::shape_rows(nf, bestv));
+        std::fflush(stderr);
+    }
+    *variant = bestv;
+    return DK_OK;
+}
+
 // Run samples [first, first+count) of level `level` (coupled pair if `pair`), reduce the
 // per-sample values in chunk order and return per-observable moments.
 int run_level(dk_context* ctx, const dk_problem* p, int level, bool pair, uint64_t first, uint64_t count,
@@ -394,7 +460,11 @@ int run_level(dk_context* ctx, const dk_problem* p, int level, bool pair, uint64
     A.obs_f = (const double*)Tf->obs.p;
     A.obs_c = pair ? (const double*)Tc->obs.p : nullptr;
     A.n_obs = nobs;
-    dk::LevelKind K{p->precision, pair, p->flux, true};
+    int variant = 0;
+    rc = choose_shape(ctx, p, pair, A, count, (double)nf * nf * (double)Tf->steps * (pair ? 1.0 + 1.0 / 16.0 : 1.0), s,
+                      &variant);
+    if (rc) return rc;
+    dk::LevelKind K{p->precision, pair, p->flux, true, variant};
     const size_t esize = p->precision == DK_PREC_F64 ? 8 : 4;
     while (ctx->ev_pool.size() < 2 * nchunks) {
         hipEvent_t e;
@@ -434,6 +504,7 @@ int run_level(dk_context* ctx, const dk_problem* p, int level, bool pair, uint64
         }
         st.launches += nchunks;
         st.samples += count;
+        st.rows = p->precision == DK_PREC_F32 ? dk::shape_rows(nf, variant) : (nf == 128 ? 16 : dk::shape_rows(nf, 0));
         st.cells += (double)nf * nf * (double)Tf->steps * (pair ? 1.0 + 1.0 / 16.0 : 1.0) * (double)count;
     }
     for (uint64_t k = 0; k < nchunks; ++k) {
@@ -956,6 +1027,8 @@ int dk_context_stats(dk_context* ctx, dk_kernel_stats* out, int32_t max)
             r.samples = kv.second.samples;
             r.kernel_ms = kv.second.ms;
             r.cell_updates = kv.second.cells;
+            r.rows = kv.second.rows;
+            r.reserved = 0;
         }
         ++k;
     }
@@ -966,9 +1039,23 @@ int dk_context_reset(dk_context* ctx, int32_t drop_tables)
 {
     if (!ctx) return fail(DK_EINVAL, "context is NULL");
     ctx->stats.clear();
-    if (drop_tables) ctx->problems.clear();
+    if (drop_tables) {
+        ctx->problems.clear();
+        ctx->tuned.clear();
+    }
     return DK_OK;
 }
+
+int dk_context_set_shape(dk_context* ctx, int32_t n, int32_t variant)
+{
+    if (!ctx) return fail(DK_EINVAL, "context is NULL");
+    if (variant >= 0 && dk::shape_rows(n, variant) == 0) return fail(DK_EINVAL, "no tile-shape variant %d for n = %d", variant, n);
+    if (variant < 0) ctx->forced_shape.erase(n);
+    else ctx->forced_shape[n] = variant;
+    return DK_OK;
+}
+
+int dk_shape_rows(int32_t n, int32_t variant) { return dk::shape_rows(n, variant); }
 
 int dk_mlmc_level_pair(dk_context* ctx, const dk_problem* problem, int32_t level, uint64_t first_sample,
                        uint64_t n_samples, uint32_t stream_tag, dk_moments* sums_out, double* per_sample_out, void* stream)

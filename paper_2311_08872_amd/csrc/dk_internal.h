@@ -38,11 +38,14 @@ struct LevelKind {
     bool pair;              // coupled fine/coarse pair
     int flux;               // DK_FLUX_*
     bool noise;             // false: noise-free mean-field run
+    int shape = 0;          // tile-shape variant (FP32 noisy kernels; see shape_rows)
 };
 
 // Returns hipSuccess, or hipErrorInvalidValue when no kernel exists for the size.
 hipError_t launch_level(const LevelKind& k, const LevelArgs& a, hipStream_t s);
 bool level_supported(int nf);
+// rows per lane of tile-shape variant v for grid size nf, 0 if the variant does not exist
+int shape_rows(int nf, int v);
 
 // Ordered, compensated per-observable moment sums of a per-sample buffer.
 // out: device [n_obs][DK_NMOM][2] (sum, compensation).

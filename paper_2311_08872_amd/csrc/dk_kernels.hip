@@ -6,8 +6,9 @@
 // the coarse grid, so every fine site of a coarse cell's right-most 2x2 block B-> is local).
 // Per fine step:
 //   1. the lane draws the normals of its first and last row and publishes those rows'
-//      density and y-noise to LDS (the only LDS traffic);
-//   2. after a barrier it reads the rows above and below its block;
+//      density and y-noise to LDS (the only LDS traffic; double-buffered by step parity, so
+//      one barrier per step suffices);
+//   2. after the barrier it reads the rows above and below its block;
 //   3. it sweeps its rows top to bottom: Philox + Box--Muller for the next row, the x-halo
 //      (one column each side) from the neighbouring lanes by ds_bpermute, then the explicit
 //      EM update of eq. (FullyDiscreteDK) with b0 = 0, b1 = 1:
@@ -62,6 +63,10 @@ struct FineNoise {
     uint32_t pair_base;      // site-pair index of the tile's row 0, first column pair
     uint32_t pairs_per_row;  // n / 2
     Real (*Z)[C / 2 > 0 ? C / 2 : 1][2];
+    Real (*pend)[C / 2 > 0 ? C / 2 : 1][2];   // row sums waiting for the other row of their coarse cell
+
+    // order in which tile_step draws the rows: 0, R-1, then 1 .. R-2
+    static constexpr int gen(int i) { return i == 0 ? 0 : (i == R - 1 ? 1 : i + 1); }
 
     template <int I>
     __device__ __forceinline__ void row(Real (&w0)[C], Real (&w1)[C])
@@ -80,8 +85,22 @@ struct FineNoise {
             w0[2 * cp + 1] = b0;
             w1[2 * cp + 1] = b1;
             if constexpr (PAIR) {
-                Z[I / 2][cp][0] += Real(a0) + Real(b0);
-                Z[I / 2][cp][1] += Real(a1) + Real(b1);
+                // each coarse cell adds (even-row sum + odd-row sum) once per fine step, whatever the
+                // order in which the two rows are drawn
+                const Real s0 = Real(a0) + Real(b0), s1 = Real(a1) + Real(b1);
+                constexpr int partner = (I % 2 == 0) ? I + 1 : I - 1;
+                if constexpr (gen(partner) < gen(I)) {
+                    constexpr int ev = (I % 2 == 0) ? I : partner;
+                    const Real e0 = (I == ev) ? s0 : pend[partner][cp][0];
+                    const Real e1 = (I == ev) ? s1 : pend[partner][cp][1];
+                    const Real o0 = (I == ev) ? pend[partner][cp][0] : s0;
+                    const Real o1 = (I == ev) ? pend[partner][cp][1] : s1;
+                    Z[I / 2][cp][0] += e0 + o0;
+                    Z[I / 2][cp][1] += e1 + o1;
+                } else {
+                    pend[I][cp][0] = s0;
+                    pend[I][cp][1] = s1;
+                }
             }
         }
     }
@@ -129,11 +148,14 @@ struct RowLoop {
 //   halo: this sample's LDS area, [G][2 (top,bottom)][2 (rho, w1)][NN]
 //   g, G: row group of the lane and number of groups; cl: column lane; NN: grid width
 // ---------------------------------------------------------------------------------------
-template <typename Real, int R, int C, int FLUX, bool NOISE, bool COMP, class Noise>
+template <typename Real, int R, int C, int FLUX, bool NOISE, bool COMP, bool ONE_BARRIER, class Noise>
 __device__ __forceinline__ void tile_step(Real (&rho)[R][C], Real (&cmp)[R][C], Noise& noise, const Real a, const Real kappa,
                                           Real* __restrict__ halo, const int g, const int G, const int cl,
                                           const int NN, const int addr_l, const int addr_r)
 {
+    // Every rounding step of the update is written out (fma where intended), so a cell's value
+    // does not depend on how the compiler schedules a particular tile shape.
+#pragma clang fp contract(off)
     Real w0_first[C], w1_first[C], w0_last[C], w1_last[C];
     if constexpr (NOISE) {
         noise.template row<0>(w0_first, w1_first);
@@ -165,7 +187,9 @@ __device__ __forceinline__ void tile_step(Real (&rho)[R][C], Real (&cmp)[R][C], 
             w1_dn[c] = below[NN + c];
         }
     }
-    __syncthreads();
+    // With a double-buffered halo (alternating by step) the next step writes the other buffer,
+    // and its barrier orders those writes after every lane's reads of this one.
+    if constexpr (!ONE_BARRIER) __syncthreads();
 
     Real rprev[C];     // old density of row i-1
     Real F1prev[C];    // y-flux of row i-1 (central) / of edge (i-1, i) (staggered)
@@ -228,7 +252,7 @@ __device__ __forceinline__ void tile_step(Real (&rho)[R][C], Real (&cmp)[R][C], 
         for (int c = 0; c < C; ++c) {
             const Real left = (c > 0) ? rho[i][(c > 0) ? c - 1 : 0] : rl;
             const Real right = (c + 1 < C) ? rho[i][(c + 1 < C) ? c + 1 : 0] : rr;
-            const Real lap = (left + right) + (rprev[c] + rnext[c]) - Real(4) * rho[i][c];
+            const Real lap = fma(Real(-4), rho[i][c], (left + right) + (rprev[c] + rnext[c]));
             Real d = a * lap;
             if constexpr (NOISE) {
                 Real div;
@@ -240,7 +264,7 @@ __device__ __forceinline__ void tile_step(Real (&rho)[R][C], Real (&cmp)[R][C], 
                     const Real fl = (c > 0) ? F0[(c > 0) ? c - 1 : 0] : F0l;
                     div = (F0[c] - fl) + (F1n[c] - F1prev[c]);
                 }
-                d = d + kappa * div;
+                d = fma(kappa, div, d);
             }
             if constexpr (COMP) {
                 // compensated (Kahan) accumulation of the increment: the rounding error of the
@@ -335,7 +359,8 @@ level_kernel(const LevelArgs A)
     static_assert(!PAIR || (R % 2 == 0 && C % 2 == 0), "pairs need even tiles");
     static_assert(TS <= 64 || TS % 64 == 0, "sample lanes");
 
-    __shared__ Real halo[SPW][G * 4 * NF];
+    // fine halo double-buffered by step parity, then the coarse halo
+    __shared__ Real halo[SPW][2 * G * 4 * NF + (PAIR ? G * 4 * NC : 0)];
     __shared__ double red[(SPW * TS + 63) / 64];
 
     const int tid = threadIdx.x;
@@ -380,6 +405,7 @@ level_kernel(const LevelArgs A)
             }
     }
 
+    Real pend[R][C / 2 > 0 ? C / 2 : 1][2];
     const NoiseKey key = make_key(A.seed, A.tag, A.level_id, sample);
     const Real a = (Real)A.a, kf = (Real)A.kf, kc = (Real)A.kc;
     Real* my_halo = &halo[sw][0];
@@ -390,11 +416,14 @@ level_kernel(const LevelArgs A)
     auto fine_step = [&](int m) {
         if constexpr (NOISE) {
             FineNoise<Real, R, C, PAIR> fn{key, (uint32_t)m, (uint32_t)(col0 / 2 + row0 * (NF / 2)),
-                                           (uint32_t)(NF / 2), PAIR ? (Real(*)[C / 2 > 0 ? C / 2 : 1][2])Z : nullptr};
-            tile_step<Real, R, C, FLUX, true, COMP>(rho, rho_cmp, fn, a, kf, my_halo, g, G, cl, NF, addr_l, addr_r);
+                                           (uint32_t)(NF / 2), PAIR ? (Real(*)[C / 2 > 0 ? C / 2 : 1][2])Z : nullptr,
+                                           pend};
+            tile_step<Real, R, C, FLUX, true, COMP, true>(rho, rho_cmp, fn, a, kf, my_halo + (m & 1) * G * 4 * NF, g, G,
+                                                          cl, NF, addr_l, addr_r);
         } else {
             NoNoise<Real, C> nn;
-            tile_step<Real, R, C, FLUX, false, false>(rho, rho_cmp, nn, a, Real(0), my_halo, g, G, cl, NF, addr_l, addr_r);
+            tile_step<Real, R, C, FLUX, false, false, true>(rho, rho_cmp, nn, a, Real(0), my_halo + (m & 1) * G * 4 * NF, g,
+                                                            G, cl, NF, addr_l, addr_r);
         }
     };
     if constexpr (PAIR) {
@@ -404,7 +433,8 @@ level_kernel(const LevelArgs A)
 #pragma unroll 1
             for (int j = 0; j < 4; ++j) fine_step(4 * mc + j);
             CoarseNoise<Real, RC, CCc> cn{Z};
-            tile_step<Real, RC, CCc, FLUX, NOISE, COMP>(rhoc, rhoc_cmp, cn, a, kc, my_halo, g, G, cl, NC, addr_l, addr_r);
+            tile_step<Real, RC, CCc, FLUX, NOISE, COMP, false>(rhoc, rhoc_cmp, cn, a, kc, my_halo + 2 * G * 4 * NF, g, G,
+                                                                 cl, NC, addr_l, addr_r);
 #pragma unroll
             for (int i = 0; i < RC; ++i)
 #pragma unroll
@@ -444,37 +474,92 @@ level_kernel(const LevelArgs A)
 }
 
 // ---------------------------------------------------------------------------------------
-// Tile shapes per grid size: (rows per lane R, columns per lane C, samples per block SPW)
+// Tile shapes.  A lane owns C = 2 columns and R rows; a sample uses (NF/2) x (NF/R) lanes and a
+// block holds SPW samples (about 256 lanes).  Several R per grid size are compiled for the FP32
+// noisy kernels; the host picks one by timing them (autotuning).  The other variants (FP64 state,
+// noise-free mean field) use the first shape.
 // ---------------------------------------------------------------------------------------
-template <int NF> struct Shape;
-template <> struct Shape<8>   { static constexpr int R = 2,  C = 2, SPW = 16; };
-template <> struct Shape<16>  { static constexpr int R = 4,  C = 2, SPW = 8; };
-template <> struct Shape<32>  { static constexpr int R = 8,  C = 2, SPW = 4; };
-template <> struct Shape<64>  { static constexpr int R = 16, C = 2, SPW = 2; };
-template <> struct Shape<128> { static constexpr int R = 16, C = 2, SPW = 1; };
+template <int NF, int R>
+struct ShapeOf {
+    static constexpr int C = 2;
+    static constexpr int TS = (NF / C) * (NF / R);
+    static constexpr int SPW = TS >= 256 ? 1 : 256 / TS;
+};
 
-template <typename Real, int NF, bool PAIR, int FLUX, bool NOISE>
-static hipError_t launch_shape(const LevelArgs& A, hipStream_t s)
+// rows per lane of shape variant v for grid size nf (0 = no such variant); variant 0 is the
+// default (8 rows: the fastest measured on MI355X for every grid size of the hierarchy)
+int shape_rows(int nf, int v)
 {
-    using S = Shape<NF>;
-    constexpr int TS = (NF / S::C) * (NF / S::R);
+    switch (nf) {
+        case 8: { const int r[] = {8, 2, 4}; return v < 3 ? r[v] : 0; }
+        case 16: { const int r[] = {8, 4, 2}; return v < 3 ? r[v] : 0; }
+        case 32: { const int r[] = {8, 4, 16}; return v < 3 ? r[v] : 0; }
+        case 64: { const int r[] = {8, 16}; return v < 2 ? r[v] : 0; }
+        case 128: { const int r[] = {8, 16}; return v < 2 ? r[v] : 0; }
+        default: return 0;
+    }
+}
+
+template <typename Real, int NF, int R, bool PAIR, int FLUX, bool NOISE>
+static hipError_t launch_R(const LevelArgs& A, hipStream_t s)
+{
+    using S = ShapeOf<NF, R>;
     const uint64_t blocks = (A.count + S::SPW - 1) / S::SPW;
     if (blocks == 0) return hipSuccess;
     if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((level_kernel<Real, NF, S::R, S::C, PAIR, FLUX, NOISE, S::SPW>), dim3((unsigned)blocks),
-                       dim3(S::SPW * TS), 0, s, A);
+    hipLaunchKernelGGL((level_kernel<Real, NF, R, S::C, PAIR, FLUX, NOISE, S::SPW>), dim3((unsigned)blocks),
+                       dim3(S::SPW * S::TS), 0, s, A);
     return hipGetLastError();
 }
 
+template <typename Real, int NF, bool PAIR, int FLUX, bool NOISE>
+static hipError_t launch_variants(const LevelArgs& A, int v, hipStream_t s)
+{
+    constexpr bool TUNED = std::is_same<Real, float>::value && NOISE;
+    if (!TUNED) v = 0;
+    if constexpr (NF == 8) {
+        if constexpr (TUNED) {
+            if (v == 1) return launch_R<Real, 8, 2, PAIR, FLUX, NOISE>(A, s);
+            if (v == 2) return launch_R<Real, 8, 4, PAIR, FLUX, NOISE>(A, s);
+        }
+        return launch_R<Real, 8, 8, PAIR, FLUX, NOISE>(A, s);
+    } else if constexpr (NF == 16) {
+        if constexpr (TUNED) {
+            if (v == 1) return launch_R<Real, 16, 4, PAIR, FLUX, NOISE>(A, s);
+            if (v == 2) return launch_R<Real, 16, 2, PAIR, FLUX, NOISE>(A, s);
+        }
+        return launch_R<Real, 16, 8, PAIR, FLUX, NOISE>(A, s);
+    } else if constexpr (NF == 32) {
+        if constexpr (TUNED) {
+            if (v == 1) return launch_R<Real, 32, 4, PAIR, FLUX, NOISE>(A, s);
+            if (v == 2) return launch_R<Real, 32, 16, PAIR, FLUX, NOISE>(A, s);
+        }
+        return launch_R<Real, 32, 8, PAIR, FLUX, NOISE>(A, s);
+    } else if constexpr (NF == 64) {
+        if constexpr (TUNED) {
+            if (v == 1) return launch_R<Real, 64, 16, PAIR, FLUX, NOISE>(A, s);
+        }
+        return launch_R<Real, 64, 8, PAIR, FLUX, NOISE>(A, s);
+    } else {
+        if constexpr (TUNED) {
+            if (v == 1) return launch_R<Real, 128, 16, PAIR, FLUX, NOISE>(A, s);
+            return launch_R<Real, 128, 8, PAIR, FLUX, NOISE>(A, s);
+        } else {
+            // FP64 states: 8-row groups would need more LDS than a CU has
+            return launch_R<Real, 128, 16, PAIR, FLUX, NOISE>(A, s);
+        }
+    }
+}
+
 template <typename Real, bool PAIR, int FLUX, bool NOISE>
-static hipError_t launch_nf(const LevelArgs& A, hipStream_t s)
+static hipError_t launch_nf(const LevelArgs& A, int v, hipStream_t s)
 {
     switch (A.nf) {
-        case 8: return launch_shape<Real, 8, PAIR, FLUX, NOISE>(A, s);
-        case 16: return launch_shape<Real, 16, PAIR, FLUX, NOISE>(A, s);
-        case 32: return launch_shape<Real, 32, PAIR, FLUX, NOISE>(A, s);
-        case 64: return launch_shape<Real, 64, PAIR, FLUX, NOISE>(A, s);
-        case 128: return launch_shape<Real, 128, PAIR, FLUX, NOISE>(A, s);
+        case 8: return launch_variants<Real, 8, PAIR, FLUX, NOISE>(A, v, s);
+        case 16: return launch_variants<Real, 16, PAIR, FLUX, NOISE>(A, v, s);
+        case 32: return launch_variants<Real, 32, PAIR, FLUX, NOISE>(A, v, s);
+        case 64: return launch_variants<Real, 64, PAIR, FLUX, NOISE>(A, v, s);
+        case 128: return launch_variants<Real, 128, PAIR, FLUX, NOISE>(A, v, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -483,20 +568,21 @@ bool level_supported(int nf) { return nf == 8 || nf == 16 || nf == 32 || nf == 6
 
 hipError_t launch_level(const LevelKind& k, const LevelArgs& A, hipStream_t s)
 {
+    const int v = k.shape;
     if (!k.noise) {
         // noise-free FP64 mean field, single path
-        return launch_nf<double, false, DK_FLUX_CENTRAL, false>(A, s);
+        return launch_nf<double, false, DK_FLUX_CENTRAL, false>(A, 0, s);
     }
     const bool f64 = k.precision == DK_PREC_F64;
     const bool stag = k.flux == DK_FLUX_STAGGERED;
-    if (!f64 && !stag) return k.pair ? launch_nf<float, true, DK_FLUX_CENTRAL, true>(A, s)
-                                     : launch_nf<float, false, DK_FLUX_CENTRAL, true>(A, s);
-    if (!f64 && stag) return k.pair ? launch_nf<float, true, DK_FLUX_STAGGERED, true>(A, s)
-                                    : launch_nf<float, false, DK_FLUX_STAGGERED, true>(A, s);
-    if (f64 && !stag) return k.pair ? launch_nf<double, true, DK_FLUX_CENTRAL, true>(A, s)
-                                    : launch_nf<double, false, DK_FLUX_CENTRAL, true>(A, s);
-    return k.pair ? launch_nf<double, true, DK_FLUX_STAGGERED, true>(A, s)
-                  : launch_nf<double, false, DK_FLUX_STAGGERED, true>(A, s);
+    if (!f64 && !stag) return k.pair ? launch_nf<float, true, DK_FLUX_CENTRAL, true>(A, v, s)
+                                     : launch_nf<float, false, DK_FLUX_CENTRAL, true>(A, v, s);
+    if (!f64 && stag) return k.pair ? launch_nf<float, true, DK_FLUX_STAGGERED, true>(A, v, s)
+                                    : launch_nf<float, false, DK_FLUX_STAGGERED, true>(A, v, s);
+    if (f64 && !stag) return k.pair ? launch_nf<double, true, DK_FLUX_CENTRAL, true>(A, 0, s)
+                                    : launch_nf<double, false, DK_FLUX_CENTRAL, true>(A, 0, s);
+    return k.pair ? launch_nf<double, true, DK_FLUX_STAGGERED, true>(A, 0, s)
+                  : launch_nf<double, false, DK_FLUX_STAGGERED, true>(A, 0, s);
 }
 
 // ---------------------------------------------------------------------------------------
