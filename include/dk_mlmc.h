@@ -289,6 +289,13 @@ int dk_context_reset(dk_context* ctx, int32_t drop_tables);
 int dk_context_set_shape(dk_context* ctx, int32_t n, int32_t variant);
 int dk_shape_rows(int32_t n, int32_t variant);
 
+/* Grids larger than 128 x 128 (multiples of 64) run on the streaming kernel: the FP32 state
+ * stays in HBM (double-buffered), each launch advances 64 x 64 tiles with a 4-cell halo by 4
+ * fine steps (one coarse step for pairs), regenerating the halo's noise.  Its fields are
+ * bit-identical to the resident kernel's.  dk_context_set_streaming(ctx, 1) routes every level
+ * of size >= 64 through it (for comparison); field output is not available there. */
+int dk_context_set_streaming(dk_context* ctx, int32_t on);
+
 /* Description of the last error on the calling thread (static storage, never NULL). */
 const char* dk_last_error(void);
 

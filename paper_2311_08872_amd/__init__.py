@@ -134,6 +134,10 @@ class Context:
         """Force tile-shape variant `variant` for grid size n (-1: automatic)."""
         _check(self.lib.dk_context_set_shape(self.h, n, variant))
 
+    def set_streaming(self, on: bool):
+        """Route levels of size >= 64 through the HBM-streaming kernel (comparison / testing)."""
+        _check(self.lib.dk_context_set_streaming(self.h, int(on)))
+
     @staticmethod
     def shape_rows(n: int, variant: int) -> int:
         return L.load().dk_shape_rows(n, variant)

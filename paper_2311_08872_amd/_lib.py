@@ -92,6 +92,7 @@ SIGNATURES = {
     "dk_context_reset": (C.c_int, [C.c_void_p, C.c_int32]),
     "dk_context_set_shape": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "dk_shape_rows": (C.c_int, [C.c_int32, C.c_int32]),
+    "dk_context_set_streaming": (C.c_int, [C.c_void_p, C.c_int32]),
     "dk_last_error": (C.c_char_p, []),
     "dk_version": (C.c_char_p, []),
     "dk_abi_sizes": (C.c_int, [C.POINTER(C.c_int32), C.c_int32]),

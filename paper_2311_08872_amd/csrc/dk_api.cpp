@@ -202,6 +202,7 @@ struct dk_context {
     int device = 0;
     std::map<std::pair<int, int>, KStat> stats;
     std::map<int, int> forced_shape;          // grid size -> tile-shape variant
+    bool force_stream = false;                // run every level with the streaming kernel
     std::map<long, int> tuned;                // (nf, pair, flux) -> variant chosen by timing
     std::vector<std::pair<int, double>> tune_log;   // (variant, ms) of the last tuning
     std::vector<hipEvent_t> ev_pool;
@@ -209,6 +210,7 @@ struct dk_context {
     DevBuf moments;        // [chunks][n_obs][DK_NMOM][2]
     DevBuf mf0, mf1;       // mean-field streaming buffers
     DevBuf scratch_c;      // inner products
+    DevBuf st_f[2][2], st_c[2][2];   // streaming state: [buffer][rho, cmp] fine / coarse
     std::vector<double> host_mom;
     // learned control variate
     dk::cnn::Workspace cnn;
@@ -404,6 +406,102 @@ int choose_shape(dk_context* ctx, const dk_problem* p, bool pair, const dk::Leve
     return DK_OK;
 }
 
+// Grids beyond the resident kernel: state in HBM, batches of samples, one launch per coarse step
+// (4 fine steps; single-level runs end with a shorter launch), then the observables.
+int run_stream(dk_context* ctx, const dk_problem* p, int level, bool pair, uint64_t first, uint64_t count, uint32_t tag,
+               const dk::LevelArgs& A, dk_moments* sums_out, double* per_sample_out, hipStream_t s,
+               double* cell_updates, uint64_t nchunks_unused, uint64_t ch_unused, size_t mom_stride)
+{
+    const int nf = A.nf, nc = nf / 2;
+    const int nobs = p->n_obs;
+    const size_t nn = (size_t)nf * nf, ncc = (size_t)nc * nc;
+    const size_t per_sample_bytes = 2 * 2 * 4 * (nn + (pair ? ncc : 0));
+    uint64_t B = std::max<uint64_t>(1, (4ull << 30) / per_sample_bytes);
+    B = std::min<uint64_t>({B, count, 4096ull});
+    int rc;
+    for (int b = 0; b < 2; ++b)
+        for (int k = 0; k < 2; ++k) {
+            if ((rc = ctx->st_f[b][k].ensure(4 * nn * B))) return rc;
+            if (pair && (rc = ctx->st_c[b][k].ensure(4 * ncc * B))) return rc;
+        }
+    const uint64_t nbatch = (count + B - 1) / B;
+    if (!per_sample_out && (rc = ctx->per_sample.ensure(sizeof(double) * 2 * nobs * B))) return rc;
+    if ((rc = ctx->moments.ensure(sizeof(double) * mom_stride * nbatch))) return rc;
+    while (ctx->ev_pool.size() < 2 * nbatch) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        ctx->ev_pool.push_back(e);
+    }
+    const bool log = std::getenv("DK_LOG") != nullptr;
+    const int steps = A.steps;
+    for (uint64_t bi = 0; bi < nbatch; ++bi) {
+        const uint64_t b0 = bi * B;
+        const int c = (int)std::min<uint64_t>(B, count - b0);
+        double* out = per_sample_out ? per_sample_out + b0 * nobs * 2 : (double*)ctx->per_sample.p;
+        HIP_TRY(hipEventRecord(ctx->ev_pool[2 * bi], s));
+        HIP_TRY(dk::launch_stream_init((const float*)A.rho0_f, nf, c, (float*)ctx->st_f[0][0].p, (float*)ctx->st_f[0][1].p, s));
+        if (pair)
+            HIP_TRY(dk::launch_stream_init((const float*)A.rho0_c, nc, c, (float*)ctx->st_c[0][0].p,
+                                           (float*)ctx->st_c[0][1].p, s));
+        dk::StreamArgs S{};
+        S.n = nf; S.level_id = A.level_id; S.tag = A.tag; S.seed = A.seed; S.first = first + b0; S.count = c;
+        S.a = (float)A.a; S.kf = (float)A.kf; S.kc = (float)A.kc;
+        int cur = 0;
+        for (int m0 = 0; m0 < steps; m0 += 4) {
+            S.m0 = m0;
+            S.ksteps = std::min(4, steps - m0);
+            S.do_coarse = pair ? 1 : 0;
+            S.rho_in = (const float*)ctx->st_f[cur][0].p; S.cmp_in = (const float*)ctx->st_f[cur][1].p;
+            S.rho_out = (float*)ctx->st_f[1 - cur][0].p; S.cmp_out = (float*)ctx->st_f[1 - cur][1].p;
+            if (pair) {
+                S.rhoc_in = (const float*)ctx->st_c[cur][0].p; S.cmpc_in = (const float*)ctx->st_c[cur][1].p;
+                S.rhoc_out = (float*)ctx->st_c[1 - cur][0].p; S.cmpc_out = (float*)ctx->st_c[1 - cur][1].p;
+            }
+            HIP_TRY(dk::launch_stream_step(S, pair, p->flux, s));
+            cur = 1 - cur;
+        }
+        HIP_TRY(dk::launch_stream_observe((const float*)ctx->st_f[cur][0].p, nf, c, A.phi_f, A.obs_f, nobs, A.h2f, out, 0, s));
+        if (pair)
+            HIP_TRY(dk::launch_stream_observe((const float*)ctx->st_c[cur][0].p, nc, c, A.phi_c, A.obs_c, nobs, A.h2c, out, 1, s));
+        else
+            HIP_TRY(dk::launch_zero_slot(out, c, nobs, 1, s));
+        HIP_TRY(hipEventRecord(ctx->ev_pool[2 * bi + 1], s));
+        HIP_TRY(dk::launch_moments(out, (uint64_t)c, nobs, (double*)ctx->moments.p + bi * mom_stride, s));
+        if (log && nbatch > 1) {
+            HIP_TRY(hipEventSynchronize(ctx->ev_pool[2 * bi + 1]));
+            std::fprintf(stderr, "[dk] level %d%s (streamed %dx%d) batch %llu/%llu (%d samples)\n", level, pair ? " pair" : "",
+                         nf, nf, (unsigned long long)(bi + 1), (unsigned long long)nbatch, c);
+            std::fflush(stderr);
+        }
+    }
+    ctx->host_mom.resize(mom_stride * nbatch);
+    HIP_TRY(hipMemcpyAsync(ctx->host_mom.data(), ctx->moments.p, sizeof(double) * mom_stride * nbatch,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const double cells_per_sample = (double)nn * (double)steps * (pair ? 1.0 + 1.0 / 16.0 : 1.0);
+    {
+        KStat& st = ctx->stats[std::make_pair(level, pair ? 1 : 0)];
+        for (uint64_t k = 0; k < nbatch; ++k) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, ctx->ev_pool[2 * k], ctx->ev_pool[2 * k + 1]));
+            st.ms += ms;
+        }
+        st.launches += nbatch;
+        st.samples += count;
+        st.cells += cells_per_sample * (double)count;
+        st.rows = -1;   // streamed
+    }
+    for (uint64_t k = 0; k < nbatch; ++k) {
+        const uint64_t c = std::min(B, count - k * B);
+        for (int j = 0; j < nobs; ++j) merge_moments(sums_out[j], &ctx->host_mom[k * mom_stride + j * DK_NMOM * 2], c);
+    }
+    for (int j = 0; j < nobs; ++j)
+        for (int m = 0; m < DK_NMOM; ++m)
+            if (!std::isfinite(mom_value(sums_out[j], m))) return fail(DK_ENUMERIC, "non-finite sample values on level %d", level);
+    if (cell_updates) *cell_updates += cells_per_sample * (double)count;
+    return DK_OK;
+}
+
 // Run samples [first, first+count) of level `level` (coupled pair if `pair`), reduce the
 // per-sample values in chunk order and return per-observable moments.
 int run_level(dk_context* ctx, const dk_problem* p, int level, bool pair, uint64_t first, uint64_t count,
@@ -417,7 +515,13 @@ int run_level(dk_context* ctx, const dk_problem* p, int level, bool pair, uint64
     if (count > 0 && first + count < first) return fail(DK_EINVAL, "sample range overflows");
     if (first + count > (1ull << 48)) return fail(DK_EINVAL, "sample index beyond 2^48");
     const int nf = p->n0 << level;
-    if (!dk::level_supported(nf)) return fail(DK_EUNSUPPORTED, "grid %d x %d: no resident kernel for this size", nf, nf);
+    const bool stream = !dk::level_supported(nf) || (ctx->force_stream && dk::stream_supported(nf));
+    if (stream) {
+        if (!dk::stream_supported(nf))
+            return fail(DK_EUNSUPPORTED, "grid %d x %d: neither the resident nor the streaming kernel supports it", nf, nf);
+        if (p->precision != DK_PREC_F32) return fail(DK_EUNSUPPORTED, "the streaming kernel has an FP32 state only");
+        if (field_f || field_c) return fail(DK_EUNSUPPORTED, "field output is not available for streamed grids");
+    }
     LevelTables* Tf = nullptr;
     LevelTables* Tc = nullptr;
     rc = ensure_level(ctx, p, level, &Tf, s);
@@ -460,6 +564,9 @@ int run_level(dk_context* ctx, const dk_problem* p, int level, bool pair, uint64
     A.obs_f = (const double*)Tf->obs.p;
     A.obs_c = pair ? (const double*)Tc->obs.p : nullptr;
     A.n_obs = nobs;
+    if (stream)
+        return run_stream(ctx, p, level, pair, first, count, tag, A, sums_out, per_sample_out, s, cell_updates, nchunks, ch,
+                          mom_stride);
     int variant = 0;
     rc = choose_shape(ctx, p, pair, A, count, (double)nf * nf * (double)Tf->steps * (pair ? 1.0 + 1.0 / 16.0 : 1.0), s,
                       &variant);
@@ -1056,6 +1163,13 @@ int dk_context_set_shape(dk_context* ctx, int32_t n, int32_t variant)
 }
 
 int dk_shape_rows(int32_t n, int32_t variant) { return dk::shape_rows(n, variant); }
+
+int dk_context_set_streaming(dk_context* ctx, int32_t on)
+{
+    if (!ctx) return fail(DK_EINVAL, "context is NULL");
+    ctx->force_stream = on != 0;
+    return DK_OK;
+}
 
 int dk_mlmc_level_pair(dk_context* ctx, const dk_problem* problem, int32_t level, uint64_t first_sample,
                        uint64_t n_samples, uint32_t stream_tag, dk_moments* sums_out, double* per_sample_out, void* stream)

@@ -66,6 +66,31 @@ hipError_t launch_noise_dump(uint64_t seed, uint32_t tag, int level, int n, uint
                              uint32_t n_samples, int first_step, int n_steps, float* out,
                              hipStream_t s);
 
+// Streaming level kernel (state in HBM, 4-step temporal blocking, 64 x 64 tiles), FP32 state.
+struct StreamArgs {
+    int n;                  // fine grid points per axis (a multiple of 64)
+    int level_id;
+    uint32_t tag;
+    uint64_t seed;
+    uint64_t first;         // first sample of the batch
+    int count;              // samples in the batch (grid.y)
+    int m0;                 // first fine step of this launch
+    int ksteps;             // fine steps of this launch (4 for pairs)
+    int do_coarse;          // pairs: 1 = take the coarse step after the fine steps
+    float a, kf, kc;
+    const float *rho_in, *cmp_in;      // [count][n][n]
+    float *rho_out, *cmp_out;
+    const float *rhoc_in, *cmpc_in;    // [count][n/2][n/2]
+    float *rhoc_out, *cmpc_out;
+};
+bool stream_supported(int nf);
+hipError_t launch_stream_step(const StreamArgs& A, bool pair, int flux, hipStream_t s);
+hipError_t launch_stream_init(const float* rho0, int n, int count, float* rho, float* cmp, hipStream_t s);
+hipError_t launch_stream_copy(const float* a, const float* b, size_t total, float* a2, float* b2, hipStream_t s);
+hipError_t launch_stream_observe(const float* rho, int n, int count, const double* phi, const double* obs, int n_obs,
+                                 double h2, double* out, int slot, hipStream_t s);
+hipError_t launch_zero_slot(double* out, int count, int n_obs, int slot, hipStream_t s);
+
 // Noise-free FP64 stepping for grids that do not fit on chip: one launch per step.
 hipError_t launch_meanfield_stream(int n, double a, int steps, double* buf0, double* buf1,
                                    double** result, hipStream_t s);

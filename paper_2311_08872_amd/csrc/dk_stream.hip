@@ -1,0 +1,346 @@
+// dk_stream.hip -- the level kernel for grids that do not fit on chip (n >= 256; any multiple
+// of 64 works), with the state in HBM and 4-step temporal blocking.
+//
+// One launch advances a batch of samples by up to 4 fine steps -- for coupled pairs exactly the
+// 4 fine steps of one coarse step, followed by that coarse step.  Each block owns a 64 x 64 fine
+// tile of one sample and loads it with a 4-cell halo (72 x 72) into LDS.  The noise of the halo
+// is regenerated from the counter-based generator (it is a pure function of site and step), so
+// no noise is exchanged; the valid region shrinks by one cell per step.  The state is
+// double-buffered in HBM (read buffer / write buffer alternate by launch), so neighbouring tiles
+// never read cells another block is writing.
+//
+// The per-cell arithmetic (explicit FMAs, Kahan-compensated increment, coarse-noise sums added
+// as (even-row block sum + odd-row block sum)) is the same operation sequence as the resident
+// kernel, so both produce bit-identical fields.
+//
+// Lane work: a block of 256 threads owns the 36 x 36 = 1296 2x2 blocks of the extended tile
+// (thread t owns blocks t, t + 256, ...); each 2x2 block is two Philox calls per step (one per
+// horizontal site pair) and holds its cells' compensation terms and its coarse cell's noise sum
+// in registers.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dk_internal.h"
+#include "dk_rng.h"
+
+namespace dk {
+
+namespace {
+constexpr int TT = 64;               // fine tile interior
+constexpr int HH = 4;                // halo = fine steps per launch
+constexpr int EXT = TT + 2 * HH;     // 72
+constexpr int NBS = EXT / 2;         // 36 blocks per side
+constexpr int NBLK = NBS * NBS;      // 1296
+constexpr int THREADS = 256;
+constexpr int BPT = (NBLK + THREADS - 1) / THREADS;   // 6
+constexpr int CT = TT / 2;           // coarse tile interior (32)
+constexpr int CEXT = CT + 2;         // coarse tile with a 1-cell halo (34)
+
+__device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+__device__ __forceinline__ float psq(float x) { return x > 0.0f ? __builtin_amdgcn_sqrtf(x) : 0.0f; }
+}  // namespace
+
+template <int FLUX, bool PAIR>
+__global__ void __launch_bounds__(THREADS) stream_kernel(const StreamArgs A)
+{
+#pragma clang fp contract(off)
+    __shared__ float sr[EXT * EXT];
+    __shared__ float sf0[EXT * EXT];
+    __shared__ float sf1[EXT * EXT];
+    const int n = A.n;
+    const int tiles_x = n / TT;
+    const int tile = blockIdx.x;
+    const int sidx = blockIdx.y;
+    const int tx0 = (tile % tiles_x) * TT, ty0 = (tile / tiles_x) * TT;
+    const uint64_t sample = A.first + sidx;
+    const size_t nn = (size_t)n * n;
+    const float* rin = A.rho_in + sidx * nn;
+    const float* cin = A.cmp_in + sidx * nn;
+    float* rout = A.rho_out + sidx * nn;
+    float* cout = A.cmp_out + sidx * nn;
+    const int t = threadIdx.x;
+    const NoiseKey key = make_key(A.seed, A.tag, A.level_id, sample);
+    const uint32_t ppr = (uint32_t)(n / 2);
+
+    float cmp[BPT][4], Z[BPT][2];
+    // load the extended tile
+#pragma unroll
+    for (int k = 0; k < BPT; ++k) {
+        const int b = t + k * THREADS;
+        Z[k][0] = 0.f;
+        Z[k][1] = 0.f;
+        if (b < NBLK) {
+            const int bx = b % NBS, by = b / NBS;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int ex = 2 * bx + (q & 1), ey = 2 * by + (q >> 1);
+                const int gx = wrapi(tx0 + ex - HH, n), gy = wrapi(ty0 + ey - HH, n);
+                sr[ey * EXT + ex] = rin[(size_t)gy * n + gx];
+                cmp[k][q] = cin[(size_t)gy * n + gx];
+            }
+        }
+    }
+    __syncthreads();
+
+    const float a = A.a, kappa = A.kf;
+    for (int j = 0; j < A.ksteps; ++j) {
+        const uint32_t m = (uint32_t)(A.m0 + j);
+        // noise is needed on the flux region [j, EXT - j) and, for pairs, on the blocks whose
+        // coarse cell is in the coarse tile plus its halo (ext [2, EXT - 2))
+        const int lo = PAIR ? (j < 2 ? j : 2) : j;
+        const int hi = EXT - lo;
+#pragma unroll
+        for (int k = 0; k < BPT; ++k) {
+            const int b = t + k * THREADS;
+            if (b >= NBLK) continue;
+            const int bx = b % NBS, by = b / NBS;
+            if (2 * bx + 2 <= lo || 2 * bx >= hi || 2 * by + 2 <= lo || 2 * by >= hi) continue;
+            float w0[4], w1[4];
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int gy = wrapi(ty0 + 2 * by + r - HH, n);
+                const int gx = wrapi(tx0 + 2 * bx - HH, n);   // even
+                uint32_t idx = (uint32_t)(gx / 2) + ppr * (uint32_t)gy;
+                float a0, a1, b0, b1;
+                site_pair_normals(key, idx, m, a0, a1, b0, b1);
+                w0[2 * r] = a0; w1[2 * r] = a1; w0[2 * r + 1] = b0; w1[2 * r + 1] = b1;
+            }
+            if constexpr (PAIR) {
+                if (bx >= 1 && bx < NBS - 1 && by >= 1 && by < NBS - 1) {
+                    Z[k][0] += (w0[0] + w0[1]) + (w0[2] + w0[3]);
+                    Z[k][1] += (w1[0] + w1[1]) + (w1[2] + w1[3]);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int ex = 2 * bx + (q & 1), ey = 2 * by + (q >> 1);
+                if (ex < j || ex >= EXT - j || ey < j || ey >= EXT - j) continue;
+                const float rv = sr[ey * EXT + ex];
+                if (FLUX == DK_FLUX_CENTRAL) {
+                    const float sq = psq(rv);
+                    sf0[ey * EXT + ex] = sq * w0[q];
+                    sf1[ey * EXT + ex] = sq * w1[q];
+                } else {
+                    const float rx = ex + 1 < EXT ? sr[ey * EXT + ex + 1] : rv;
+                    const float ry = ey + 1 < EXT ? sr[(ey + 1) * EXT + ex] : rv;
+                    sf0[ey * EXT + ex] = psq(0.5f * (rv + rx)) * w0[q];
+                    sf1[ey * EXT + ex] = psq(0.5f * (rv + ry)) * w1[q];
+                }
+            }
+        }
+        __syncthreads();
+        // update region [j + 1, EXT - j - 1)
+        float nv[BPT][4];
+#pragma unroll
+        for (int k = 0; k < BPT; ++k) {
+            const int b = t + k * THREADS;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) nv[k][q] = 0.f;
+            if (b >= NBLK) continue;
+            const int bx = b % NBS, by = b / NBS;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int ex = 2 * bx + (q & 1), ey = 2 * by + (q >> 1);
+                if (ex <= j || ex >= EXT - j - 1 || ey <= j || ey >= EXT - j - 1) continue;
+                const int c = ey * EXT + ex;
+                const float rv = sr[c];
+                const float lap = fmaf(-4.0f, rv, (sr[c - 1] + sr[c + 1]) + (sr[c - EXT] + sr[c + EXT]));
+                float div;
+                if (FLUX == DK_FLUX_CENTRAL) div = (sf0[c + 1] - sf0[c - 1]) + (sf1[c + EXT] - sf1[c - EXT]);
+                else div = (sf0[c] - sf0[c - 1]) + (sf1[c] - sf1[c - EXT]);
+                const float d = fmaf(kappa, div, a * lap);
+                const float y = d - cmp[k][q];
+                const float tv = rv + y;
+                cmp[k][q] = (tv - rv) - y;
+                nv[k][q] = tv;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < BPT; ++k) {
+            const int b = t + k * THREADS;
+            if (b >= NBLK) continue;
+            const int bx = b % NBS, by = b / NBS;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int ex = 2 * bx + (q & 1), ey = 2 * by + (q >> 1);
+                if (ex <= j || ex >= EXT - j - 1 || ey <= j || ey >= EXT - j - 1) continue;
+                sr[ey * EXT + ex] = nv[k][q];
+            }
+        }
+        __syncthreads();
+    }
+    // write back the interior
+#pragma unroll
+    for (int k = 0; k < BPT; ++k) {
+        const int b = t + k * THREADS;
+        if (b >= NBLK) continue;
+        const int bx = b % NBS, by = b / NBS;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int ex = 2 * bx + (q & 1), ey = 2 * by + (q >> 1);
+            if (ex < HH || ex >= EXT - HH || ey < HH || ey >= EXT - HH) continue;
+            const size_t g = (size_t)(ty0 + ey - HH) * n + (tx0 + ex - HH);
+            rout[g] = sr[ey * EXT + ex];
+            cout[g] = cmp[k][q];
+        }
+    }
+    if constexpr (PAIR) {
+        if (!A.do_coarse) return;
+        // one coarse EM step with the restricted noise Z (coarse tile + 1 halo cell), reusing LDS
+        const int nc = n / 2;
+        const size_t ncc = (size_t)nc * nc;
+        const float* rcin = A.rhoc_in + sidx * ncc;
+        const float* ccin = A.cmpc_in + sidx * ncc;
+        float* rcout = A.rhoc_out + sidx * ncc;
+        float* ccout = A.cmpc_out + sidx * ncc;
+        const int cx0 = tx0 / 2, cy0 = ty0 / 2;
+        __syncthreads();
+        float* scr = sr;                 // [CEXT][CEXT]
+        float* scf0 = sf0;
+        float* scf1 = sf1;
+        for (int c = t; c < CEXT * CEXT; c += THREADS) {
+            const int ex = c % CEXT, ey = c / CEXT;
+            scr[c] = rcin[(size_t)wrapi(cy0 + ey - 1, nc) * nc + wrapi(cx0 + ex - 1, nc)];
+        }
+        __syncthreads();
+        // fluxes of the coarse cells in the halo region: block (bx, by) <-> coarse ext (bx - 1, by - 1)
+        const float kc = A.kc;
+#pragma unroll
+        for (int k = 0; k < BPT; ++k) {
+            const int b = t + k * THREADS;
+            if (b >= NBLK) continue;
+            const int bx = b % NBS, by = b / NBS;
+            if (bx < 1 || bx >= NBS - 1 || by < 1 || by >= NBS - 1) continue;
+            const int ex = bx - 1, ey = by - 1;
+            const int c = ey * CEXT + ex;
+            const float rv = scr[c];
+            if (FLUX == DK_FLUX_CENTRAL) {
+                const float sq = psq(rv);
+                scf0[c] = sq * Z[k][0];
+                scf1[c] = sq * Z[k][1];
+            } else {
+                const float rx = ex + 1 < CEXT ? scr[c + 1] : rv;
+                const float ry = ey + 1 < CEXT ? scr[c + CEXT] : rv;
+                scf0[c] = psq(0.5f * (rv + rx)) * Z[k][0];
+                scf1[c] = psq(0.5f * (rv + ry)) * Z[k][1];
+            }
+        }
+        __syncthreads();
+        for (int c = t; c < CT * CT; c += THREADS) {
+            const int ix = c % CT, iy = c / CT;
+            const int e = (iy + 1) * CEXT + (ix + 1);
+            const size_t g = (size_t)(cy0 + iy) * nc + (cx0 + ix);
+            const float rv = scr[e];
+            const float lap = fmaf(-4.0f, rv, (scr[e - 1] + scr[e + 1]) + (scr[e - CEXT] + scr[e + CEXT]));
+            float div;
+            if (FLUX == DK_FLUX_CENTRAL) div = (scf0[e + 1] - scf0[e - 1]) + (scf1[e + CEXT] - scf1[e - CEXT]);
+            else div = (scf0[e] - scf0[e - 1]) + (scf1[e] - scf1[e - CEXT]);
+            const float d = fmaf(kc, div, a * lap);
+            const float cm = ccin[g];
+            const float y = d - cm;
+            const float tv = rv + y;
+            rcout[g] = tv;
+            ccout[g] = (tv - rv) - y;
+        }
+    }
+}
+
+// state initialisation: rho = rho0 table, compensation 0
+__global__ void stream_init_kernel(const float* __restrict__ rho0, size_t nn, int count, float* __restrict__ rho,
+                                   float* __restrict__ cmp)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nn * (size_t)count) return;
+    rho[i] = rho0[i % nn];
+    cmp[i] = 0.f;
+}
+
+// copy the coarse state when a launch does no coarse step (keeps the read/write buffers in step)
+__global__ void stream_copy_kernel(const float* __restrict__ a, const float* __restrict__ b, size_t total,
+                                   float* __restrict__ a2, float* __restrict__ b2)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    a2[i] = a[i];
+    b2[i] = b[i];
+}
+
+// observables of final fields: one block per sample; out[s][j][slot]
+__global__ void __launch_bounds__(256) stream_observe_kernel(const float* __restrict__ rho, int n, int count,
+                                                             const double* __restrict__ phi, const double* __restrict__ obs,
+                                                             int n_obs, double h2, double* __restrict__ out, int slot)
+{
+    const int s = blockIdx.x;
+    if (s >= count) return;
+    const size_t nn = (size_t)n * n;
+    const float* r = rho + s * nn;
+    __shared__ double red[4];
+    for (int j = 0; j < n_obs; ++j) {
+        const double* ph = phi + j * nn;
+        double acc = 0.0;
+        for (size_t i = threadIdx.x; i < nn; i += 256) acc = fma((double)r[i], ph[i], acc);
+        for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const double L = (red[0] + red[1]) + (red[2] + red[3]);
+            const double X = obs[3 * j] * (h2 * L - obs[3 * j + 1]);
+            out[((size_t)s * n_obs + j) * 2 + slot] = obs[3 * j + 2] != 0.0 ? X * X : X;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void zero_slot_kernel(double* out, int count, int n_obs, int slot)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count * n_obs) return;
+    out[(size_t)i * 2 + slot] = 0.0;
+}
+
+bool stream_supported(int nf) { return nf >= 64 && nf % TT == 0; }
+
+hipError_t launch_stream_step(const StreamArgs& A, bool pair, int flux, hipStream_t s)
+{
+    const dim3 grid((unsigned)((A.n / TT) * (A.n / TT)), (unsigned)A.count);
+    if (pair) {
+        if (flux == DK_FLUX_CENTRAL) hipLaunchKernelGGL((stream_kernel<DK_FLUX_CENTRAL, true>), grid, dim3(THREADS), 0, s, A);
+        else hipLaunchKernelGGL((stream_kernel<DK_FLUX_STAGGERED, true>), grid, dim3(THREADS), 0, s, A);
+    } else {
+        if (flux == DK_FLUX_CENTRAL) hipLaunchKernelGGL((stream_kernel<DK_FLUX_CENTRAL, false>), grid, dim3(THREADS), 0, s, A);
+        else hipLaunchKernelGGL((stream_kernel<DK_FLUX_STAGGERED, false>), grid, dim3(THREADS), 0, s, A);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_init(const float* rho0, int n, int count, float* rho, float* cmp, hipStream_t s)
+{
+    const size_t total = (size_t)n * n * count;
+    hipLaunchKernelGGL(stream_init_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, rho0, (size_t)n * n,
+                       count, rho, cmp);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_copy(const float* a, const float* b, size_t total, float* a2, float* b2, hipStream_t s)
+{
+    hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a, b, total, a2, b2);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_observe(const float* rho, int n, int count, const double* phi, const double* obs, int n_obs,
+                                 double h2, double* out, int slot, hipStream_t s)
+{
+    hipLaunchKernelGGL(stream_observe_kernel, dim3(count), dim3(256), 0, s, rho, n, count, phi, obs, n_obs, h2, out, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_slot(double* out, int count, int n_obs, int slot, hipStream_t s)
+{
+    const int total = count * n_obs;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_slot_kernel, dim3((total + 255) / 256), dim3(256), 0, s, out, count, n_obs, slot);
+    return hipGetLastError();
+}
+
+}  // namespace dk

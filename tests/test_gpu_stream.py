@@ -1,0 +1,72 @@
+"""The HBM-streaming level kernel (grids beyond 128^2; 4-step temporal blocking) against the
+resident kernel on grids both can run (same fields bit for bit, so the observables agree to
+the FP64 reduction order), and against the FP64 oracle on 256^2 and 1024^2 grids with short
+horizons (tolerance as for the resident kernel, 1e-5 of the batch RMS)."""
+import numpy as np
+import pytest
+
+import dk_workloads as W
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2311_08872_amd as dk  # noqa: E402
+
+
+def banner(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+@pytest.mark.parametrize("flux", [W.FLUX_CENTRAL, W.FLUX_STAGGERED])
+@pytest.mark.parametrize("level", [3, 4])
+def test_stream_matches_resident(level, flux):
+    p = W.config2(N=3e3).with_(flux=flux, T=0.05 / 16)
+    banner(f"stream vs resident level={level} flux={flux}")
+    res = dk.Context(0)
+    st = dk.Context(0)
+    st.set_streaming(True)
+    for coupled in (True, False):
+        f = dk.level_pair if coupled else (lambda pr, l, a, b, per_sample, ctx: dk.mc_level(pr, l, a, b, per_sample=per_sample, ctx=ctx))
+        _, a = f(p, level, 5, 77, per_sample=True, ctx=res)
+        _, b = f(p, level, 5, 77, per_sample=True, ctx=st)
+        torch.cuda.synchronize()
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        assert np.allclose(a, b, rtol=1e-11, atol=1e-13), (coupled, np.max(np.abs(a - b)))
+        assert st.stats()[-1]["rows"] == -1 or any(s["rows"] == -1 for s in st.stats())
+    res.close()
+    st.close()
+
+
+def scaled_err(gpu, ref):
+    rms = np.sqrt(np.mean(ref ** 2, axis=0, keepdims=True))
+    return float(np.max(np.abs(gpu - ref) / np.maximum(np.abs(ref), rms)))
+
+
+def test_stream_256_pair_matches_oracle():
+    """Config-3 finest pair (256^2 / 128^2) with a 64-step horizon (hierarchy starting at 128^2)."""
+    p = W.config3(N=1e5).with_(n0=128, levels=2)
+    p = p.with_(T=p.tau(1) * 64)
+    assert p.n(1) == 256 and p.steps(1) == 64
+    banner("stream 256^2 pair vs oracle")
+    _, ps = dk.level_pair(p, 1, 3, 8, per_sample=True)
+    torch.cuda.synchronize()
+    ref = oracle.run_range(oracle.OracleProblem(p), 1, 3, 8)
+    assert scaled_err(ps.cpu().numpy(), ref) <= 1e-5
+
+
+def test_stream_1024_pair_matches_oracle():
+    """Config-5 finest pair (1024^2 / 512^2) with a 16-step horizon, 2 samples."""
+    p = W.config5().with_(n0=512, levels=2)
+    p = p.with_(T=p.tau(1) * 16, steps_policy=W.STEPS_EXACT)
+    assert p.n(1) == 1024 and p.steps(1) == 16
+    banner("stream 1024^2 pair vs oracle")
+    _, ps = dk.level_pair(p, 1, 0, 2, per_sample=True)
+    torch.cuda.synchronize()
+    ref = oracle.run_range(oracle.OracleProblem(p), 1, 0, 2)
+    gpu = ps.cpu().numpy()
+    rel = np.abs(gpu - ref) / np.maximum(np.abs(ref), 1e-3)
+    assert float(rel.max()) <= 1e-5, rel.max()
