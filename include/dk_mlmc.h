@@ -147,6 +147,11 @@ typedef struct {
     const float* cv_params;   /* host [levels][DK_CNN_NPARAM] network parameters, or NULL         */
     uint32_t cv_level_mask;   /* bit l set: level l >= 1 uses the learned control variate         */
     int32_t cv_ratio;         /* independent coarse-only paths per pair (default 4)               */
+    int32_t round_mode;       /* 0: levels one after another (per-launch timing);
+                                 1: each round's levels concurrently, one stream per level;
+                                 2: as 1, captured into a hipGraph launched once per round.
+                                 The samples and results are identical in all modes.               */
+    int32_t reserved;
 } dk_mlmc_opts;
 
 typedef struct {
@@ -295,6 +300,13 @@ int dk_shape_rows(int32_t n, int32_t variant);
  * bit-identical to the resident kernel's.  dk_context_set_streaming(ctx, 1) routes every level
  * of size >= 64 through it (for comparison); field output is not available there. */
 int dk_context_set_streaming(dk_context* ctx, int32_t on);
+
+/* Noise-free scheme (rho <- rho + (mu/2) Lap_h rho, the discrete mean-field dynamics of Sec. 3)
+ * for `steps` steps on a batch of FP32 fields rho (DEVICE [batch][n][n], updated in place;
+ * work: DEVICE scratch of the same size).  n a multiple of 4.  kernel_ms (optional) receives
+ * the event time of the steps.  Memory-bound: 8 B of HBM traffic per cell update. */
+int dk_heat_steps(dk_context* ctx, int32_t n, int32_t batch, int32_t steps, double mu, float* rho, float* work,
+                  double* kernel_ms, void* stream);
 
 /* Description of the last error on the calling thread (static storage, never NULL). */
 const char* dk_last_error(void);

@@ -198,7 +198,7 @@ def mc_level(problem, level: int, first: int, n: int, per_sample: bool = False, 
 
 
 def _opts(m_pilot=1000, L_start=2, alpha=2.0, max_rounds=1000, plain_mc_level=-1, max_samples=0, cv_params=None,
-          cv_level_mask=0, cv_ratio=4, _keep=None):
+          cv_level_mask=0, cv_ratio=4, round_mode=0, _keep=None):
     ptr = None
     if cv_params is not None:
         arr = np.ascontiguousarray(cv_params, dtype=np.float32)
@@ -206,7 +206,7 @@ def _opts(m_pilot=1000, L_start=2, alpha=2.0, max_rounds=1000, plain_mc_level=-1
             _keep.append(arr)
         ptr = arr.ctypes.data_as(C.POINTER(C.c_float))
     return L.dk_mlmc_opts(m_pilot, L_start, alpha, max_rounds, plain_mc_level, max_samples, ptr, cv_level_mask,
-                          cv_ratio)
+                          cv_ratio, round_mode, 0)
 
 
 def _result_dict(r: L.dk_mlmc_result, nobs: int, rc: int) -> dict:
@@ -327,6 +327,19 @@ def cv_train(problem, level: int, n_train: int = 1 << 16, epochs: int = 10, batc
                                hist.ctypes.data_as(C.POINTER(C.c_double)), val.ctypes.data_as(C.POINTER(C.c_double)),
                                ctx.stream()))
     return {"params": prm, "loss": hist.tolist(), "var_Y": val[0], "var_Y_minus_r": val[1], "var_r": val[2]}
+
+
+def heat_steps(rho, steps: int, mu: float, ctx: Context | None = None) -> float:
+    """dk_heat_steps: noise-free steps of a batch of FP32 fields rho [batch, n, n] (device,
+    in place); returns the kernel time in ms."""
+    ctx = ctx or default_context()
+    torch = _torch()
+    assert rho.dtype == torch.float32 and rho.is_contiguous()
+    work = torch.empty_like(rho)
+    ms = C.c_double()
+    _check(ctx.lib.dk_heat_steps(ctx.h, rho.shape[-1], rho.shape[0], steps, mu, _ptr(rho), _ptr(work), C.byref(ms),
+                                 ctx.stream()))
+    return ms.value
 
 
 def alg1_host(eps: float, L_max: int, cost, sampler: Callable[[int, int, int], np.ndarray], **opts) -> dict:

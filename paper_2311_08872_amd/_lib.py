@@ -44,7 +44,8 @@ class dk_moments(C.Structure):
 class dk_mlmc_opts(C.Structure):
     _fields_ = [("m_pilot", C.c_int32), ("L_start", C.c_int32), ("alpha", C.c_double), ("max_rounds", C.c_int32),
                 ("plain_mc_level", C.c_int32), ("max_samples", C.c_uint64), ("cv_params", C.POINTER(C.c_float)),
-                ("cv_level_mask", C.c_uint32), ("cv_ratio", C.c_int32)]
+                ("cv_level_mask", C.c_uint32), ("cv_ratio", C.c_int32), ("round_mode", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class dk_mlmc_result(C.Structure):
@@ -93,6 +94,8 @@ SIGNATURES = {
     "dk_context_set_shape": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "dk_shape_rows": (C.c_int, [C.c_int32, C.c_int32]),
     "dk_context_set_streaming": (C.c_int, [C.c_void_p, C.c_int32]),
+    "dk_heat_steps": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_void_p, C.c_void_p,
+                                C.POINTER(C.c_double), C.c_void_p]),
     "dk_last_error": (C.c_char_p, []),
     "dk_version": (C.c_char_p, []),
     "dk_abi_sizes": (C.c_int, [C.POINTER(C.c_int32), C.c_int32]),

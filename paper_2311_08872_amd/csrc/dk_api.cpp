@@ -203,6 +203,14 @@ struct dk_context {
     std::map<std::pair<int, int>, KStat> stats;
     std::map<int, int> forced_shape;          // grid size -> tile-shape variant
     bool force_stream = false;                // run every level with the streaming kernel
+    // concurrent rounds: one stream per level, fork/join events, per-level buffers
+    hipStream_t lvl_stream[DK_MAX_LEVELS] = {};
+    hipEvent_t fork_ev = nullptr, join_ev[DK_MAX_LEVELS] = {};
+    DevBuf rnd_ps[DK_MAX_LEVELS], rnd_mom[DK_MAX_LEVELS];
+    hipEvent_t rnd_t0 = nullptr, rnd_t1 = nullptr;
+    hipStream_t cap_stream = nullptr;         // private stream that round graphs are captured on
+    double round_ms = 0;
+    uint64_t round_graphs = 0;
     std::map<long, int> tuned;                // (nf, pair, flux) -> variant chosen by timing
     std::vector<std::pair<int, double>> tune_log;   // (variant, ms) of the last tuning
     std::vector<hipEvent_t> ev_pool;
@@ -629,6 +637,149 @@ int run_level(dk_context* ctx, const dk_problem* p, int level, bool pair, uint64
 }
 
 // ------------------------------------------------------------------------------------------
+// One Algorithm-1 round of resident levels at once: every level's batches go to its own
+// stream (forked from and joined to the caller's stream), so levels of very different size
+// fill the GPU together; mode 2 captures the whole round into a hipGraph and launches it once.
+// The per-sample values and the chunking are those of run_level, so results are identical.
+// ------------------------------------------------------------------------------------------
+struct RoundJob {
+    int level = 0;
+    bool pair = false;
+    uint64_t first = 0, count = 0, ch = 0, nchunks = 0;
+    dk::LevelArgs A{};
+    dk::LevelKind K{};
+    double cells_per_sample = 0;
+};
+
+int run_round(dk_context* ctx, const dk_problem* p, int L, const uint64_t* first, const uint64_t* count, uint32_t tag,
+              int mode, std::vector<dk_moments>& sums /* [(L+1) * n_obs] */, hipStream_t s, double* cell_updates)
+{
+    const int nobs = p->n_obs;
+    const size_t mom_stride = (size_t)nobs * DK_NMOM * 2;
+    std::vector<RoundJob> jobs;
+    for (int l = 0; l <= L; ++l) {
+        for (int j = 0; j < nobs; ++j) std::memset(&sums[(size_t)l * nobs + j], 0, sizeof(dk_moments));
+        if (count[l] == 0) continue;
+        RoundJob J;
+        J.level = l;
+        J.pair = l >= 1;
+        J.first = first[l];
+        J.count = count[l];
+        const int nf = p->n0 << l;
+        LevelTables *Tf = nullptr, *Tc = nullptr;
+        int rc = ensure_level(ctx, p, l, &Tf, s);
+        if (rc) return rc;
+        if (J.pair && (rc = ensure_level(ctx, p, l - 1, &Tc, s))) return rc;
+        J.cells_per_sample = (double)nf * nf * (double)Tf->steps * (J.pair ? 1.0 + 1.0 / 16.0 : 1.0);
+        J.ch = chunk_size(nobs, J.cells_per_sample);
+        J.nchunks = (J.count + J.ch - 1) / J.ch;
+        dk::LevelArgs& A = J.A;
+        A.nf = nf; A.level_id = l; A.tag = tag; A.seed = p->seed; A.steps = (int)Tf->steps; A.a = 0.5 * p->mu;
+        const double sig_f = std::sqrt(Tf->tau);
+        A.kf = noise_coeff(p, Tf->h, sig_f);
+        A.kc = J.pair ? noise_coeff(p, Tc->h, 0.5 * sig_f) : 0.0;
+        A.h2f = Tf->h * Tf->h;
+        A.h2c = J.pair ? Tc->h * Tc->h : 0.0;
+        A.rho0_f = Tf->rho0.p;
+        A.rho0_c = J.pair ? Tc->rho0.p : nullptr;
+        A.phi_f = (const double*)Tf->phi.p;
+        A.phi_c = J.pair ? (const double*)Tc->phi.p : nullptr;
+        A.obs_f = (const double*)Tf->obs.p;
+        A.obs_c = J.pair ? (const double*)Tc->obs.p : nullptr;
+        A.n_obs = nobs;
+        int variant = 0;
+        if ((rc = choose_shape(ctx, p, J.pair, A, J.count, J.cells_per_sample, s, &variant))) return rc;
+        J.K = dk::LevelKind{p->precision, J.pair, p->flux, true, variant};
+        if ((rc = ctx->rnd_ps[l].ensure(sizeof(double) * 2 * nobs * std::min(J.ch, J.count)))) return rc;
+        if ((rc = ctx->rnd_mom[l].ensure(sizeof(double) * mom_stride * J.nchunks))) return rc;
+        if (!ctx->lvl_stream[l]) {
+            HIP_TRY(hipStreamCreateWithFlags(&ctx->lvl_stream[l], hipStreamNonBlocking));
+            HIP_TRY(hipEventCreateWithFlags(&ctx->join_ev[l], hipEventDisableTiming));
+        }
+        jobs.push_back(J);
+    }
+    if (jobs.empty()) return DK_OK;
+    if (!ctx->fork_ev) {
+        HIP_TRY(hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
+        HIP_TRY(hipEventCreate(&ctx->rnd_t0));
+        HIP_TRY(hipEventCreate(&ctx->rnd_t1));
+    }
+    if (mode == 2 && !ctx->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    // the caller's stream may be the null stream, which cannot be captured: graphs are captured
+    // on a private stream and launched on the caller's
+    const hipStream_t o = mode == 2 ? ctx->cap_stream : s;
+    auto enqueue = [&]() -> int {
+        HIP_TRY(hipEventRecord(ctx->fork_ev, o));
+        for (RoundJob& J : jobs) {
+            hipStream_t ls = ctx->lvl_stream[J.level];
+            HIP_TRY(hipStreamWaitEvent(ls, ctx->fork_ev, 0));
+            for (uint64_t k = 0; k < J.nchunks; ++k) {
+                dk::LevelArgs A = J.A;
+                const uint64_t b = k * J.ch;
+                A.first = J.first + b;
+                A.count = std::min(J.ch, J.count - b);
+                A.out = (double*)ctx->rnd_ps[J.level].p;
+                A.field_f = nullptr;
+                A.field_c = nullptr;
+                HIP_TRY(dk::launch_level(J.K, A, ls));
+                HIP_TRY(dk::launch_moments(A.out, A.count, nobs, (double*)ctx->rnd_mom[J.level].p + k * mom_stride, ls));
+            }
+            HIP_TRY(hipEventRecord(ctx->join_ev[J.level], ls));
+            HIP_TRY(hipStreamWaitEvent(o, ctx->join_ev[J.level], 0));
+        }
+        return DK_OK;
+    };
+    HIP_TRY(hipEventRecord(ctx->rnd_t0, s));
+    if (mode == 2) {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        HIP_TRY(hipStreamBeginCapture(o, hipStreamCaptureModeThreadLocal));
+        const int rc = enqueue();
+        hipGraph_t g2 = nullptr;
+        const hipError_t ec = hipStreamEndCapture(o, &g2);
+        if (rc) { if (g2) (void)hipGraphDestroy(g2); return rc; }
+        if (ec != hipSuccess) return fail(DK_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+        graph = g2;
+        HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        HIP_TRY(hipGraphLaunch(exec, s));
+        HIP_TRY(hipEventRecord(ctx->rnd_t1, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        ctx->round_graphs += 1;
+    } else {
+        const int rc = enqueue();
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(ctx->rnd_t1, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ctx->rnd_t0, ctx->rnd_t1));
+    ctx->round_ms += ms;
+    std::vector<double> h;
+    for (RoundJob& J : jobs) {
+        h.resize(mom_stride * J.nchunks);
+        HIP_TRY(hipMemcpy(h.data(), ctx->rnd_mom[J.level].p, sizeof(double) * h.size(), hipMemcpyDeviceToHost));
+        for (uint64_t k = 0; k < J.nchunks; ++k) {
+            const uint64_t c = std::min(J.ch, J.count - k * J.ch);
+            for (int j = 0; j < nobs; ++j)
+                merge_moments(sums[(size_t)J.level * nobs + j], &h[k * mom_stride + j * DK_NMOM * 2], c);
+        }
+        for (int j = 0; j < nobs; ++j)
+            for (int m = 0; m < DK_NMOM; ++m)
+                if (!std::isfinite(mom_value(sums[(size_t)J.level * nobs + j], m)))
+                    return fail(DK_ENUMERIC, "non-finite sample values on level %d", J.level);
+        KStat& st = ctx->stats[std::make_pair(J.level, J.pair ? 1 : 0)];
+        st.launches += J.nchunks;
+        st.samples += J.count;
+        st.cells += J.cells_per_sample * (double)J.count;
+        st.rows = dk::shape_rows(J.A.nf, J.K.shape);
+        if (cell_updates) *cell_updates += J.cells_per_sample * (double)J.count;
+    }
+    return DK_OK;
+}
+
+// ------------------------------------------------------------------------------------------
 // Algorithm 1 (Sec. 7), independent of how samples are produced.
 // ------------------------------------------------------------------------------------------
 dk_mlmc_opts default_opts()
@@ -651,8 +802,11 @@ double bias_remainder(const std::vector<double>& Y, int L, double alpha)
     return r / (std::pow(2.0, alpha) - 1.0);
 }
 
+// optional: all levels of one round at once; sums [L+1][2]
+typedef int (*round_sampler)(void* user, int L, const uint64_t* first, const uint64_t* count, double* sums);
+
 int alg1_core(double eps, int L_max, const double* cost, const dk_mlmc_opts& o, dk_level_sampler sampler, void* user,
-              dk_mlmc_result* out)
+              dk_mlmc_result* out, round_sampler rsampler = nullptr)
 {
     if (!(eps > 0)) return fail(DK_EINVAL, "eps must be > 0");
     if (L_max < 0 || L_max >= DK_MAX_LEVELS) return fail(DK_EINVAL, "L_max out of range");
@@ -689,16 +843,35 @@ int alg1_core(double eps, int L_max, const double* cost, const dk_mlmc_opts& o, 
         }
         if (rounds >= o.max_rounds) return fail(DK_EINVAL, "Algorithm 1 exceeded max_rounds = %d", o.max_rounds);
         ++rounds;
-        for (int l = 0; l <= L; ++l) {
-            if (target[l] <= done[l]) continue;
-            const uint64_t extra = target[l] - done[l];
-            double sums[2] = {0, 0};
-            const int rc = sampler(user, l, done[l], extra, sums);
+        if (rsampler) {
+            std::vector<uint64_t> f(L + 1), c(L + 1);
+            std::vector<double> sums(2 * (L + 1), 0.0);
+            for (int l = 0; l <= L; ++l) {
+                f[l] = done[l];
+                c[l] = target[l] > done[l] ? target[l] - done[l] : 0;
+            }
+            const int rc = rsampler(user, L, f.data(), c.data(), sums.data());
             if (rc < 0) return rc;
-            if (!std::isfinite(sums[0]) || !std::isfinite(sums[1])) return fail(DK_ENUMERIC, "non-finite sums on level %d", l);
-            nadd(s1[l], c1[l], sums[0]);
-            nadd(s2[l], c2[l], sums[1]);
-            done[l] += extra;
+            for (int l = 0; l <= L; ++l) {
+                if (c[l] == 0) continue;
+                if (!std::isfinite(sums[2 * l]) || !std::isfinite(sums[2 * l + 1]))
+                    return fail(DK_ENUMERIC, "non-finite sums on level %d", l);
+                nadd(s1[l], c1[l], sums[2 * l]);
+                nadd(s2[l], c2[l], sums[2 * l + 1]);
+                done[l] += c[l];
+            }
+        } else {
+            for (int l = 0; l <= L; ++l) {
+                if (target[l] <= done[l]) continue;
+                const uint64_t extra = target[l] - done[l];
+                double sums[2] = {0, 0};
+                const int rc = sampler(user, l, done[l], extra, sums);
+                if (rc < 0) return rc;
+                if (!std::isfinite(sums[0]) || !std::isfinite(sums[1])) return fail(DK_ENUMERIC, "non-finite sums on level %d", l);
+                nadd(s1[l], c1[l], sums[0]);
+                nadd(s2[l], c2[l], sums[1]);
+                done[l] += extra;
+            }
         }
         stats(L);
         if (std::getenv("DK_LOG")) {
@@ -857,6 +1030,7 @@ struct GpuSampler {
     uint32_t cv_mask = 0;
     int cv_ratio = 4;
     std::vector<dk_moments> zmom;       // [levels] moments of the control-variate samples
+    int round_mode = 0;                 // 0: level after level, 1: concurrent streams, 2: hipGraph per round
 };
 
 int gpu_sample(void* user, int32_t level, uint64_t first, uint64_t count, double* sums)
@@ -898,6 +1072,46 @@ int gpu_sample(void* user, int32_t level, uint64_t first, uint64_t count, double
     return DK_OK;
 }
 
+
+// A whole round: resident, non-control-variate levels together (run_round), the rest one by one.
+int gpu_round(void* user, int L, const uint64_t* first, const uint64_t* count, double* sums)
+{
+    GpuSampler& G = *(GpuSampler*)user;
+    const int nobs = G.p->n_obs;
+    std::vector<uint64_t> cnt(count, count + L + 1);
+    for (int l = 0; l <= L; ++l) {
+        const int nf = G.p->n0 << l;
+        const bool cv = l >= 1 && G.cv_params && ((G.cv_mask >> l) & 1u);
+        const bool streamed = !dk::level_supported(nf) || (G.ctx->force_stream && dk::stream_supported(nf));
+        if ((cv || streamed || G.plain_mc) && count[l] > 0) {
+            double s2[2] = {0, 0};
+            const int rc = gpu_sample(user, l, first[l], count[l], s2);
+            if (rc < 0) return rc;
+            sums[2 * l] = s2[0];
+            sums[2 * l + 1] = s2[1];
+            cnt[l] = 0;
+        }
+    }
+    std::vector<dk_moments> rs((size_t)(L + 1) * nobs);
+    const int rc = run_round(G.ctx, G.p, L, first, cnt.data(), G.tag, G.round_mode, rs, G.s, &G.cell_updates);
+    if (rc < 0) return rc;
+    for (int l = 0; l <= L; ++l) {
+        if (cnt[l] == 0) continue;
+        for (int j = 0; j < nobs; ++j) {
+            dk_moments& d = G.mom[(size_t)l * nobs + j];
+            const dk_moments& r = rs[(size_t)l * nobs + j];
+            d.count += r.count;
+            for (int k = 0; k < DK_NMOM; ++k) {
+                nadd(d.sum[k], d.comp[k], r.sum[k]);
+                d.comp[k] += r.comp[k];
+            }
+        }
+        const dk_moments& pm = rs[(size_t)l * nobs + G.p->primary_obs];
+        sums[2 * l] = mom_value(pm, DK_MOM_Y);
+        sums[2 * l + 1] = mom_value(pm, DK_MOM_Y2);
+    }
+    return DK_OK;
+}
 
 double level_cost(const dk_problem* p, long steps0, int level, bool pair)
 {
@@ -1118,6 +1332,14 @@ void dk_context_destroy(dk_context* ctx)
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    for (int l = 0; l < DK_MAX_LEVELS; ++l) {
+        if (ctx->lvl_stream[l]) (void)hipStreamDestroy(ctx->lvl_stream[l]);
+        if (ctx->join_ev[l]) (void)hipEventDestroy(ctx->join_ev[l]);
+    }
+    if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->rnd_t0) (void)hipEventDestroy(ctx->rnd_t0);
+    if (ctx->rnd_t1) (void)hipEventDestroy(ctx->rnd_t1);
     delete ctx;
 }
 
@@ -1163,6 +1385,35 @@ int dk_context_set_shape(dk_context* ctx, int32_t n, int32_t variant)
 }
 
 int dk_shape_rows(int32_t n, int32_t variant) { return dk::shape_rows(n, variant); }
+
+int dk_heat_steps(dk_context* ctx, int32_t n, int32_t batch, int32_t steps, double mu, float* rho, float* work,
+                  double* kernel_ms, void* stream)
+{
+    if (!ctx || !rho || !work) return fail(DK_EINVAL, "NULL argument");
+    if (n < 4 || n % 4 || batch < 1 || steps < 0) return fail(DK_EINVAL, "n must be a multiple of 4, batch >= 1");
+    if (!(mu > 0) || mu > 0.5) return fail(DK_EINVAL, "mu outside (0, 1/2]");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, s));
+    float* a = rho;
+    float* b = work;
+    for (int m = 0; m < steps; ++m) {
+        HIP_TRY(dk::launch_heat_f32(a, b, n, batch, (float)(0.5 * mu), s));
+        std::swap(a, b);
+    }
+    HIP_TRY(hipEventRecord(e1, s));
+    if (a != rho) HIP_TRY(hipMemcpyAsync(rho, a, sizeof(float) * (size_t)n * n * batch, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    if (kernel_ms) *kernel_ms = ms;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return DK_OK;
+}
 
 int dk_context_set_streaming(dk_context* ctx, int32_t on)
 {
@@ -1292,7 +1543,10 @@ int dk_mlmc_estimate(dk_context* ctx, const dk_problem* problem, double eps, con
             cost[l] = level_cost(problem, s0, l, true);
             if ((G.cv_mask >> l) & 1u) cost[l] += G.cv_ratio * level_cost(problem, s0, l - 1, false);
         }
-        rc = alg1_core(eps, problem->levels - 1, cost.data(), o, gpu_sample, &G, out);
+        G.round_mode = o.round_mode;
+        if (o.round_mode < 0 || o.round_mode > 2) return fail(DK_EINVAL, "round_mode must be 0, 1 or 2");
+        rc = alg1_core(eps, problem->levels - 1, cost.data(), o, gpu_sample, &G, out,
+                       o.round_mode > 0 ? gpu_round : nullptr);
         if (rc < 0) return rc;
     } else {
         // plain MC on one level: pilot, then M = ceil(2 V / eps^2) so that V / M <= eps^2 / 2

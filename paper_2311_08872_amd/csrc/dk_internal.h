@@ -84,6 +84,7 @@ struct StreamArgs {
     float *rhoc_out, *cmpc_out;
 };
 bool stream_supported(int nf);
+hipError_t launch_heat_f32(const float* in, float* out, int n, int batch, float a, hipStream_t s);
 hipError_t launch_stream_step(const StreamArgs& A, bool pair, int flux, hipStream_t s);
 hipError_t launch_stream_init(const float* rho0, int n, int count, float* rho, float* cmp, hipStream_t s);
 hipError_t launch_stream_copy(const float* a, const float* b, size_t total, float* a2, float* b2, hipStream_t s);

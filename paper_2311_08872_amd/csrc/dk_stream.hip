@@ -299,6 +299,40 @@ __global__ void zero_slot_kernel(double* out, int count, int n_obs, int slot)
     out[(size_t)i * 2 + slot] = 0.0;
 }
 
+// Noise-free FP32 step of a batch of fields (the scheme without noise, i.e. the discrete mean
+// field of many initial data at once): one thread per 4 consecutive cells of a row, 16-byte
+// loads of the row and the rows above and below, the two outer neighbours as scalars.
+__global__ void heat_f32_kernel(const float* __restrict__ in, float* __restrict__ out, int n, size_t total4, float a)
+{
+    const size_t i4 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i4 >= total4) return;
+    const int q = n / 4;
+    const size_t nn = (size_t)n * n;
+    const size_t b = i4 / ((size_t)q * n);
+    const size_t r = i4 - b * (size_t)q * n;
+    const int y = (int)(r / q), x0 = (int)(r % q) * 4;
+    const float* f = in + b * nn;
+    const int ym = y == 0 ? n - 1 : y - 1, yp = y == n - 1 ? 0 : y + 1;
+    const float4 c = *(const float4*)(f + (size_t)y * n + x0);
+    const float4 u = *(const float4*)(f + (size_t)ym * n + x0);
+    const float4 d = *(const float4*)(f + (size_t)yp * n + x0);
+    const float l = f[(size_t)y * n + (x0 == 0 ? n - 1 : x0 - 1)];
+    const float rr = f[(size_t)y * n + (x0 + 4 == n ? 0 : x0 + 4)];
+    float4 o;
+    o.x = c.x + a * fmaf(-4.0f, c.x, (l + c.y) + (u.x + d.x));
+    o.y = c.y + a * fmaf(-4.0f, c.y, (c.x + c.z) + (u.y + d.y));
+    o.z = c.z + a * fmaf(-4.0f, c.z, (c.y + c.w) + (u.z + d.z));
+    o.w = c.w + a * fmaf(-4.0f, c.w, (c.z + rr) + (u.w + d.w));
+    *(float4*)(out + b * nn + (size_t)y * n + x0) = o;
+}
+
+hipError_t launch_heat_f32(const float* in, float* out, int n, int batch, float a, hipStream_t s)
+{
+    const size_t total4 = (size_t)n * n * batch / 4;
+    hipLaunchKernelGGL(heat_f32_kernel, dim3((unsigned)((total4 + 255) / 256)), dim3(256), 0, s, in, out, n, total4, a);
+    return hipGetLastError();
+}
+
 bool stream_supported(int nf) { return nf >= 64 && nf % TT == 0; }
 
 hipError_t launch_stream_step(const StreamArgs& A, bool pair, int flux, hipStream_t s)

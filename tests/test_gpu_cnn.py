@@ -85,3 +85,17 @@ def test_training_reduces_loss_and_keeps_estimator_unbiased():
     for l in (1, 2):
         se_l = math.sqrt(plain["Vhat"][l] / plain["M"][l] + cv["Vhat"][l] / cv["M"][l])
         assert abs(plain["Yhat"][l] - cv["Yhat"][l]) < 4.5 * se_l, l
+
+
+def test_control_variate_gain_is_measured():
+    """What the trained network buys on config 2 (pair 1, coarse 8x8 input): the fraction of
+    Var(Y_1) it removes on held-out pairs is reported; it cannot be negative beyond noise and
+    the estimator's variance Var(Y - r) + Var(r)/k is compared with Var(Y)."""
+    p = W.config2(N=1e4)
+    res = dk.cv_train(p, 1, n_train=1 << 14, epochs=6, batch=256, lr=1e-3, n_val=1 << 13, seed=1)
+    vy, vd, vr = res["var_Y"], res["var_Y_minus_r"], res["var_r"]
+    print(f"[gpu] cv gain level 1: Var(Y)={vy:.4g} Var(Y-r)={vd:.4g} Var(r)={vr:.4g} "
+          f"explained={(1 - vd / vy):.3%}", flush=True)
+    se = vy * math.sqrt(2.0 / (1 << 13))
+    assert vd <= vy + 4.5 * se
+    assert vd + vr / 4 <= 1.1 * vy

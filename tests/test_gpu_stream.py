@@ -70,3 +70,19 @@ def test_stream_1024_pair_matches_oracle():
     gpu = ps.cpu().numpy()
     rel = np.abs(gpu - ref) / np.maximum(np.abs(ref), 1e-3)
     assert float(rel.max()) <= 1e-5, rel.max()
+
+
+def test_noise_free_batch_matches_fourier_multiplier():
+    """dk_heat_steps: each field evolves by the multiplier g_k^M of the noise-free scheme."""
+    import math
+    from closed_forms import A_pow
+    n, batch, steps, mu = 64, 5, 37, 0.1
+    rng = np.random.default_rng(4)
+    x = rng.random((batch, n, n)).astype(np.float32)
+    rho = torch.from_numpy(x).cuda()
+    dk.heat_steps(rho, steps, mu)
+    torch.cuda.synchronize()
+    got = rho.cpu().numpy().astype(np.float64)
+    for b in range(batch):
+        ref = A_pow(x[b].astype(np.float64), steps, mu)
+        assert np.max(np.abs(got[b] - ref)) < 1e-5
