@@ -53,30 +53,41 @@ class _Problem(C.Structure):
                 ("pad", C.c_int32), ("obs", C.POINTER(_Obs)), ("rho0", _Field), ("seed", C.c_uint64)]
 
 
+def _load(path):
+    L = C.CDLL(path)
+    dp = C.POINTER(C.c_double)
+    u32p = C.POINTER(C.c_uint32)
+    L.dko_philox_many.argtypes = [C.c_int64, u32p, u32p, u32p]
+    L.dko_gauss_many.argtypes = [C.c_int64, u32p, u32p, C.POINTER(C.c_float), C.POINTER(C.c_float)]
+    L.dko_noise_step.argtypes = [C.c_uint64, C.c_uint32, C.c_int, C.c_uint64, C.c_int, C.c_int, dp]
+    L.dko_noise_step_f32.argtypes = [C.c_uint64, C.c_uint32, C.c_int, C.c_uint64, C.c_int, C.c_int,
+                                     C.POINTER(C.c_float)]
+    L.dko_em_step.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_int, dp, dp, dp]
+    L.dko_field_grid.argtypes = [C.POINTER(_Field), C.c_double, C.c_int, dp]
+    L.dko_meanfield.argtypes = [C.POINTER(_Problem), C.c_int, dp, dp]
+    L.dko_run_single.argtypes = [C.POINTER(_Problem), C.c_int, C.c_uint64, C.c_uint32, dp, dp, dp]
+    L.dko_run_pair.argtypes = [C.POINTER(_Problem), C.c_int, C.c_uint64, C.c_uint32, dp, dp, dp,
+                               dp, dp, dp]
+    L.dko_run_range.argtypes = [C.POINTER(_Problem), C.c_int, C.c_int, C.c_uint64, C.c_uint64,
+                                C.c_uint32, dp, dp, dp]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         path = os.path.join(_HERE, "libdk_oracle.so")
         if not os.path.exists(path):
             _build.build()
-        L = C.CDLL(path)
-        dp = C.POINTER(C.c_double)
-        u32p = C.POINTER(C.c_uint32)
-        L.dko_philox_many.argtypes = [C.c_int64, u32p, u32p, u32p]
-        L.dko_gauss_many.argtypes = [C.c_int64, u32p, u32p, C.POINTER(C.c_float), C.POINTER(C.c_float)]
-        L.dko_noise_step.argtypes = [C.c_uint64, C.c_uint32, C.c_int, C.c_uint64, C.c_int, C.c_int, dp]
-        L.dko_noise_step_f32.argtypes = [C.c_uint64, C.c_uint32, C.c_int, C.c_uint64, C.c_int, C.c_int,
-                                         C.POINTER(C.c_float)]
-        L.dko_em_step.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_int, dp, dp, dp]
-        L.dko_field_grid.argtypes = [C.POINTER(_Field), C.c_double, C.c_int, dp]
-        L.dko_meanfield.argtypes = [C.POINTER(_Problem), C.c_int, dp, dp]
-        L.dko_run_single.argtypes = [C.POINTER(_Problem), C.c_int, C.c_uint64, C.c_uint32, dp, dp, dp]
-        L.dko_run_pair.argtypes = [C.POINTER(_Problem), C.c_int, C.c_uint64, C.c_uint32, dp, dp, dp,
-                                   dp, dp, dp]
-        L.dko_run_range.argtypes = [C.POINTER(_Problem), C.c_int, C.c_int, C.c_uint64, C.c_uint64,
-                                    C.c_uint32, dp, dp, dp]
-        _lib = L
+        _lib = _load(path)
     return _lib
+
+
+def use_library(path: str | None):
+    """Swap the oracle library (tests load deliberately broken builds to check that the pins
+    reject them); None restores the regular build."""
+    global _lib
+    _lib = None if path is None else _load(path)
 
 
 def _dp(a):

@@ -13,8 +13,8 @@
 // as (even-row block sum + odd-row block sum)) is the same operation sequence as the resident
 // kernel, so both produce bit-identical fields.
 //
-// Lane work: a block of 256 threads owns the 36 x 36 = 1296 2x2 blocks of the extended tile
-// (thread t owns blocks t, t + 256, ...); each 2x2 block is two Philox calls per step (one per
+// Lane work: a block of 512 threads owns the 36 x 36 = 1296 2x2 blocks of the extended tile
+// (thread t owns blocks t, t + 512, t + 1024); each 2x2 block is two Philox calls per step (one per
 // horizontal site pair) and holds its cells' compensation terms and its coarse cell's noise sum
 // in registers.
 #include <hip/hip_runtime.h>
@@ -31,8 +31,8 @@ constexpr int HH = 4;                // halo = fine steps per launch
 constexpr int EXT = TT + 2 * HH;     // 72
 constexpr int NBS = EXT / 2;         // 36 blocks per side
 constexpr int NBLK = NBS * NBS;      // 1296
-constexpr int THREADS = 256;
-constexpr int BPT = (NBLK + THREADS - 1) / THREADS;   // 6
+constexpr int THREADS = 512;
+constexpr int BPT = (NBLK + THREADS - 1) / THREADS;   // 3
 constexpr int CT = TT / 2;           // coarse tile interior (32)
 constexpr int CEXT = CT + 2;         // coarse tile with a 1-cell halo (34)
 
@@ -41,7 +41,7 @@ __device__ __forceinline__ float psq(float x) { return x > 0.0f ? __builtin_amdg
 }  // namespace
 
 template <int FLUX, bool PAIR>
-__global__ void __launch_bounds__(THREADS) stream_kernel(const StreamArgs A)
+__global__ void __launch_bounds__(THREADS, 4) stream_kernel(const StreamArgs A)
 {
 #pragma clang fp contract(off)
     __shared__ float sr[EXT * EXT];
