@@ -149,8 +149,17 @@ typedef struct {
     int32_t cv_ratio;         /* independent coarse-only paths per pair (default 4)               */
     int32_t round_mode;       /* 0: levels one after another (per-launch timing);
                                  1: each round's levels concurrently, one stream per level;
-                                 2: as 1, captured into a hipGraph launched once per round.
-                                 The samples and results are identical in all modes.               */
+                                 2: as 1, captured into a hipGraph launched once per round;
+                                 3: persistent: the round's resident FP32 levels in one launch of
+                                    one 1024-lane block per compute unit pulling (level, sample
+                                    range) tasks, finest level first, from a device counter; the
+                                    launch is a hipGraph captured once per context and replayed
+                                    (rounds above about 2e12 cell updates take one launch per
+                                    2e12).  Other levels run as in mode 0; FP64 problems run as
+                                    in mode 1.
+                                 Modes 0-2 give identical results; mode 3 uses 8 rows per lane and
+                                 sums moments per task, so its results agree with mode 0's to
+                                 rounding (per-sample paths are the same).                         */
     int32_t reserved;
 } dk_mlmc_opts;
 
@@ -195,6 +204,17 @@ int dk_mlmc_level_pair(dk_context* ctx, const dk_problem* problem, int32_t level
 int dk_mc_level(dk_context* ctx, const dk_problem* problem, int32_t level,
                 uint64_t first_sample, uint64_t n_samples,
                 dk_moments* sums_out, double* per_sample_out, void* stream);
+
+/* One round of Algorithm 1 (Sec. 7) without the algorithm around it: samples
+ * [first[l], first[l] + count[l]) of every level l <= L (level 0 single paths, l >= 1 pairs
+ * coupled by the NN restriction of Sec. 3.2) from noise stream `tag` (0-255), run as
+ * round_mode (0-3, as in dk_mlmc_opts) would run them.  first, count: host [L + 1]; sample
+ * indices < 2^48; count[l] = 0 skips level l.  sums_out: host [(L + 1) * n_obs], moments per
+ * level and observable (zero where count is 0).  For callers that drive their own estimator
+ * loop; results do not depend on round_mode except as stated for mode 3.  Errors: DK_EINVAL
+ * for bad arguments; device errors as for dk_mlmc_level_pair. */
+int dk_mlmc_round(dk_context* ctx, const dk_problem* problem, int32_t L, const uint64_t* first, const uint64_t* count,
+                  uint32_t tag, int32_t round_mode, dk_moments* sums_out, void* stream);
 
 /* Algorithm 1 of Sec. 7 to RMSE eps on the GPU (or plain MC when opts->plain_mc_level >= 0).
  * opts may be NULL (defaults).  level_moments: optional host array [levels][n_obs].
@@ -268,7 +288,10 @@ int dk_cv_train(dk_context* ctx, const dk_problem* problem, int32_t level, uint6
 
 /* Per-kernel timing of a context, measured with HIP events around every level-kernel launch
  * on the caller's stream (for profiling and roofline reports).  One record per
- * (level, coupled) pair that ran since the last reset. */
+ * (level, coupled) pair that ran since the last reset.  The persistent round kernel
+ * (round_mode 3) has the record with level = -1 (its launches, samples, time and cell updates
+ * over all levels); the per-level records of its samples carry samples and cell updates with
+ * no launches or time. */
 typedef struct {
     int32_t level;            /* fine level                                  */
     int32_t coupled;          /* 1 for NN-coupled pairs                      */
@@ -300,6 +323,12 @@ int dk_shape_rows(int32_t n, int32_t variant);
  * bit-identical to the resident kernel's.  dk_context_set_streaming(ctx, 1) routes every level
  * of size >= 64 through it (for comparison); field output is not available there. */
 int dk_context_set_streaming(dk_context* ctx, int32_t on);
+
+/* Largest work of one sampling launch, in fine + coarse cell updates (default 2e12, about 5 s
+ * on MI355X; 0 restores the default, values below 1e6 are raised to 1e6).  Longer levels are
+ * split into more launches and persistent rounds into more segments (graph replays); moment
+ * sums are then grouped differently (rounding-level differences only). */
+int dk_context_set_launch_cap(dk_context* ctx, double cells);
 
 /* Noise-free scheme (rho <- rho + (mu/2) Lap_h rho, the discrete mean-field dynamics of Sec. 3)
  * for `steps` steps on a batch of FP32 fields rho (DEVICE [batch][n][n], updated in place;

@@ -134,6 +134,10 @@ class Context:
         """Force tile-shape variant `variant` for grid size n (-1: automatic)."""
         _check(self.lib.dk_context_set_shape(self.h, n, variant))
 
+    def set_launch_cap(self, cells: float):
+        """Largest work of one sampling launch in cell updates (0 = default 2e12)."""
+        _check(self.lib.dk_context_set_launch_cap(self.h, float(cells)))
+
     def set_streaming(self, on: bool):
         """Route levels of size >= 64 through the HBM-streaming kernel (comparison / testing)."""
         _check(self.lib.dk_context_set_streaming(self.h, int(on)))
@@ -195,6 +199,21 @@ def mc_level(problem, level: int, first: int, n: int, per_sample: bool = False, 
         out = torch.empty((n, nobs, 2), dtype=torch.float64, device=f"cuda:{ctx.device}")
     _check(ctx.lib.dk_mc_level(ctx.h, cp.ref, level, first, n, sums, _ptr(out), ctx.stream()))
     return (_moments(sums), out) if per_sample else _moments(sums)
+
+
+def round_sums(problem, finest: int, first, count, tag: int = W.TAG_MLMC, round_mode: int = 0,
+               ctx: Context | None = None):
+    """dk_mlmc_round: one Algorithm-1 round of samples [first[l], first[l] + count[l]) of levels
+    0..finest in the given round mode; returns moments [finest + 1][n_obs]."""
+    ctx = ctx or default_context()
+    cp = _cp(problem)
+    nobs = len(cp.p.obs)
+    f = (C.c_uint64 * (finest + 1))(*[int(v) for v in first])
+    c = (C.c_uint64 * (finest + 1))(*[int(v) for v in count])
+    sums = (L.dk_moments * ((finest + 1) * nobs))()
+    _check(ctx.lib.dk_mlmc_round(ctx.h, cp.ref, finest, f, c, tag, round_mode, sums, ctx.stream()))
+    ms = _moments(sums)
+    return [ms[l * nobs:(l + 1) * nobs] for l in range(finest + 1)]
 
 
 def _opts(m_pilot=1000, L_start=2, alpha=2.0, max_rounds=1000, plain_mc_level=-1, max_samples=0, cv_params=None,

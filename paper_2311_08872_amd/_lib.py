@@ -71,6 +71,8 @@ SIGNATURES = {
                                      C.c_uint32, C.POINTER(dk_moments), C.c_void_p, C.c_void_p]),
     "dk_mc_level": (C.c_int, [C.c_void_p, C.POINTER(dk_problem), C.c_int32, C.c_uint64, C.c_uint64,
                               C.POINTER(dk_moments), C.c_void_p, C.c_void_p]),
+    "dk_mlmc_round": (C.c_int, [C.c_void_p, C.POINTER(dk_problem), C.c_int32, C.POINTER(C.c_uint64),
+                                C.POINTER(C.c_uint64), C.c_uint32, C.c_int32, C.POINTER(dk_moments), C.c_void_p]),
     "dk_mlmc_estimate": (C.c_int, [C.c_void_p, C.POINTER(dk_problem), C.c_double, C.POINTER(dk_mlmc_opts),
                                    C.POINTER(dk_mlmc_result), C.POINTER(dk_moments), C.c_void_p]),
     "dk_meanfield": (C.c_int, [C.c_void_p, C.POINTER(dk_problem), C.c_int32, C.POINTER(C.c_double), C.c_void_p,
@@ -93,6 +95,7 @@ SIGNATURES = {
     "dk_context_reset": (C.c_int, [C.c_void_p, C.c_int32]),
     "dk_context_set_shape": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "dk_shape_rows": (C.c_int, [C.c_int32, C.c_int32]),
+    "dk_context_set_launch_cap": (C.c_int, [C.c_void_p, C.c_double]),
     "dk_context_set_streaming": (C.c_int, [C.c_void_p, C.c_int32]),
     "dk_heat_steps": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_void_p, C.c_void_p,
                                 C.POINTER(C.c_double), C.c_void_p]),

@@ -192,6 +192,8 @@ struct ProblemTables {
 
 }  // namespace
 
+constexpr double kMaxCellsPerLaunch = 2e12;   // default cap: about 5 s of kernel time per launch
+
 struct KStat {
     uint64_t launches = 0, samples = 0;
     double ms = 0, cells = 0;
@@ -203,6 +205,7 @@ struct dk_context {
     std::map<std::pair<int, int>, KStat> stats;
     std::map<int, int> forced_shape;          // grid size -> tile-shape variant
     bool force_stream = false;                // run every level with the streaming kernel
+    double max_launch_cells = kMaxCellsPerLaunch;   // work cap of one sampling launch
     // concurrent rounds: one stream per level, fork/join events, per-level buffers
     hipStream_t lvl_stream[DK_MAX_LEVELS] = {};
     hipEvent_t fork_ev = nullptr, join_ev[DK_MAX_LEVELS] = {};
@@ -211,6 +214,16 @@ struct dk_context {
     hipStream_t cap_stream = nullptr;         // private stream that round graphs are captured on
     double round_ms = 0;
     uint64_t round_graphs = 0;
+    // persistent rounds: device tables, the queue counter, per-task moments, per-block scratch,
+    // pinned staging, and the captured graph (reset + round kernel) replayed for every segment
+    DevBuf pr_levels, pr_tasks, pr_ntasks, pr_head, pr_task_mom, pr_scratch;
+    void* pr_host = nullptr;
+    size_t pr_host_bytes = 0;
+    hipGraph_t pr_graph = nullptr;
+    hipGraphExec_t pr_exec = nullptr;
+    dk::RoundArgs pr_args{};
+    int pr_flux = -1, pr_grid = 0;
+    hipEvent_t pr_t0 = nullptr, pr_t1 = nullptr;
     std::map<long, int> tuned;                // (nf, pair, flux) -> variant chosen by timing
     std::vector<std::pair<int, double>> tune_log;   // (variant, ms) of the last tuning
     std::vector<hipEvent_t> ev_pool;
@@ -339,15 +352,14 @@ int ensure_level(dk_context* ctx, const dk_problem* p, int level, LevelTables** 
 
 constexpr uint64_t kMaxChunk = 1ull << 22;
 constexpr size_t kChunkBytes = 256ull << 20;
-constexpr double kMaxCellsPerLaunch = 2e12;   // about 5 s of kernel time per launch
 
 // Samples per launch: bounded by the per-sample output buffer and by the work of one launch
 // (long levels are split so that no launch runs for more than a few seconds).
-uint64_t chunk_size(int n_obs, double cells_per_sample)
+uint64_t chunk_size(int n_obs, double cells_per_sample, double max_cells)
 {
     uint64_t c = kChunkBytes / (16ull * n_obs);
     c = std::min<uint64_t>(c, kMaxChunk);
-    const double by_work = std::floor(kMaxCellsPerLaunch / std::max(cells_per_sample, 1.0));
+    const double by_work = std::floor(max_cells / std::max(cells_per_sample, 1.0));
     if (by_work < (double)c) c = std::max<uint64_t>(256, (uint64_t)by_work);
     return c;
 }
@@ -542,7 +554,7 @@ int run_level(dk_context* ctx, const dk_problem* p, int level, bool pair, uint64
     for (int j = 0; j < nobs; ++j) std::memset(&sums_out[j], 0, sizeof(dk_moments));
     if (count == 0) return DK_OK;
     const double cells_per_sample = (double)nf * nf * (double)Tf->steps * (pair ? 1.0 + 1.0 / 16.0 : 1.0);
-    const uint64_t ch = chunk_size(nobs, cells_per_sample);
+    const uint64_t ch = chunk_size(nobs, cells_per_sample, ctx->max_launch_cells);
     const bool log = std::getenv("DK_LOG") != nullptr;
     const uint64_t nchunks = (count + ch - 1) / ch;
     if (!per_sample_out) {
@@ -636,6 +648,35 @@ int run_level(dk_context* ctx, const dk_problem* p, int level, bool pair, uint64
     return DK_OK;
 }
 
+// Tables and coefficients of level l (a pair with level l-1 if `pair`) for the level kernels;
+// first, count and the output pointers are left to the caller.
+int level_args(dk_context* ctx, const dk_problem* p, int l, bool pair, uint32_t tag, hipStream_t s, dk::LevelArgs* out,
+               double* cells_per_sample)
+{
+    const int nf = p->n0 << l;
+    LevelTables *Tf = nullptr, *Tc = nullptr;
+    int rc = ensure_level(ctx, p, l, &Tf, s);
+    if (rc) return rc;
+    if (pair && (rc = ensure_level(ctx, p, l - 1, &Tc, s))) return rc;
+    *cells_per_sample = (double)nf * nf * (double)Tf->steps * (pair ? 1.0 + 1.0 / 16.0 : 1.0);
+    dk::LevelArgs A{};
+    A.nf = nf; A.level_id = l; A.tag = tag; A.seed = p->seed; A.steps = (int)Tf->steps; A.a = 0.5 * p->mu;
+    const double sig_f = std::sqrt(Tf->tau);
+    A.kf = noise_coeff(p, Tf->h, sig_f);
+    A.kc = pair ? noise_coeff(p, Tc->h, 0.5 * sig_f) : 0.0;
+    A.h2f = Tf->h * Tf->h;
+    A.h2c = pair ? Tc->h * Tc->h : 0.0;
+    A.rho0_f = Tf->rho0.p;
+    A.rho0_c = pair ? Tc->rho0.p : nullptr;
+    A.phi_f = (const double*)Tf->phi.p;
+    A.phi_c = pair ? (const double*)Tc->phi.p : nullptr;
+    A.obs_f = (const double*)Tf->obs.p;
+    A.obs_c = pair ? (const double*)Tc->obs.p : nullptr;
+    A.n_obs = p->n_obs;
+    *out = A;
+    return DK_OK;
+}
+
 // ------------------------------------------------------------------------------------------
 // One Algorithm-1 round of resident levels at once: every level's batches go to its own
 // stream (forked from and joined to the caller's stream), so levels of very different size
@@ -665,28 +706,11 @@ int run_round(dk_context* ctx, const dk_problem* p, int L, const uint64_t* first
         J.pair = l >= 1;
         J.first = first[l];
         J.count = count[l];
-        const int nf = p->n0 << l;
-        LevelTables *Tf = nullptr, *Tc = nullptr;
-        int rc = ensure_level(ctx, p, l, &Tf, s);
+        int rc = level_args(ctx, p, l, J.pair, tag, s, &J.A, &J.cells_per_sample);
         if (rc) return rc;
-        if (J.pair && (rc = ensure_level(ctx, p, l - 1, &Tc, s))) return rc;
-        J.cells_per_sample = (double)nf * nf * (double)Tf->steps * (J.pair ? 1.0 + 1.0 / 16.0 : 1.0);
-        J.ch = chunk_size(nobs, J.cells_per_sample);
+        J.ch = chunk_size(nobs, J.cells_per_sample, ctx->max_launch_cells);
         J.nchunks = (J.count + J.ch - 1) / J.ch;
         dk::LevelArgs& A = J.A;
-        A.nf = nf; A.level_id = l; A.tag = tag; A.seed = p->seed; A.steps = (int)Tf->steps; A.a = 0.5 * p->mu;
-        const double sig_f = std::sqrt(Tf->tau);
-        A.kf = noise_coeff(p, Tf->h, sig_f);
-        A.kc = J.pair ? noise_coeff(p, Tc->h, 0.5 * sig_f) : 0.0;
-        A.h2f = Tf->h * Tf->h;
-        A.h2c = J.pair ? Tc->h * Tc->h : 0.0;
-        A.rho0_f = Tf->rho0.p;
-        A.rho0_c = J.pair ? Tc->rho0.p : nullptr;
-        A.phi_f = (const double*)Tf->phi.p;
-        A.phi_c = J.pair ? (const double*)Tc->phi.p : nullptr;
-        A.obs_f = (const double*)Tf->obs.p;
-        A.obs_c = J.pair ? (const double*)Tc->obs.p : nullptr;
-        A.n_obs = nobs;
         int variant = 0;
         if ((rc = choose_shape(ctx, p, J.pair, A, J.count, J.cells_per_sample, s, &variant))) return rc;
         J.K = dk::LevelKind{p->precision, J.pair, p->flux, true, variant};
@@ -776,6 +800,184 @@ int run_round(dk_context* ctx, const dk_problem* p, int L, const uint64_t* first
         st.rows = dk::shape_rows(J.A.nf, J.K.shape);
         if (cell_updates) *cell_updates += J.cells_per_sample * (double)J.count;
     }
+    return DK_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// One Algorithm-1 round of resident FP32 levels in one persistent launch (round_mode 3).
+// Tasks: for each level, from the finest down, contiguous sample ranges of whole
+// block-iterations sized to about 1/8 of a block's share of one launch; segments: consecutive
+// tasks of at most the context's launch cap in cell updates (one launch each, so no launch runs for more
+// than a few seconds).  Every segment replays the same captured graph (queue reset + round
+// kernel) after its task list has been uploaded; the graph is captured again only when a
+// device buffer it points to had to grow.  Task moments are merged per level in task order.
+// ------------------------------------------------------------------------------------------
+bool round_eligible(const dk_problem* p, int l, bool force_stream)
+{
+    const int nf = p->n0 << l;
+    return p->precision == DK_PREC_F32 && p->n_obs <= dk::round_max_obs() && !force_stream &&
+           dk::round_kind(nf, l >= 1) >= 0;
+}
+
+int run_round_persistent(dk_context* ctx, const dk_problem* p, int L, const uint64_t* first, const uint64_t* count,
+                         uint32_t tag, std::vector<dk_moments>& sums /* [(L+1) * n_obs] */, hipStream_t s,
+                         double* cell_updates)
+{
+    const int nobs = p->n_obs;
+    const size_t nmom = (size_t)nobs * DK_NMOM;
+    std::vector<dk::RoundLevel> lv(L + 1);
+    std::vector<double> cps(L + 1, 0.0);
+    double total = 0;
+    for (int l = 0; l <= L; ++l) {
+        for (int j = 0; j < nobs; ++j) std::memset(&sums[(size_t)l * nobs + j], 0, sizeof(dk_moments));
+        std::memset(&lv[l], 0, sizeof(dk::RoundLevel));
+        lv[l].kind = -1;
+        if (count[l] == 0) continue;
+        if (!round_eligible(p, l, ctx->force_stream)) return fail(DK_EUNSUPPORTED, "level %d cannot join a persistent round", l);
+        int rc = level_args(ctx, p, l, l >= 1, tag, s, &lv[l].A, &cps[l]);
+        if (rc) return rc;
+        lv[l].kind = dk::round_kind(lv[l].A.nf, l >= 1);
+        lv[l].spw = dk::round_spw_of(lv[l].A.nf);
+        total += cps[l] * (double)count[l];
+    }
+    if (total == 0) return DK_OK;
+    if (ctx->pr_grid == 0) {
+        int cus = 0;
+        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+        ctx->pr_grid = std::max(1, cus) * dk::round_blocks_per_cu(p->flux);
+        HIP_TRY(hipEventCreate(&ctx->pr_t0));
+        HIP_TRY(hipEventCreate(&ctx->pr_t1));
+    }
+    const int grid = ctx->pr_grid;
+    // tasks, finest level first
+    const double cap = ctx->max_launch_cells;
+    const double per_task = std::min(total, cap) / (8.0 * grid);
+    std::vector<dk::RoundTask> tasks;
+    std::vector<double> work;
+    for (int l = L; l >= 0; --l) {
+        if (count[l] == 0) continue;
+        const uint64_t spw = (uint64_t)lv[l].spw;
+        const uint64_t iters = std::max<uint64_t>(1, (uint64_t)std::floor(per_task / (cps[l] * (double)spw)));
+        const uint64_t chunk = iters * spw;
+        for (uint64_t b = 0; b < count[l]; b += chunk) {
+            dk::RoundTask t{};
+            t.level = (uint32_t)l;
+            t.first = first[l] + b;
+            t.count = std::min(chunk, count[l] - b);
+            tasks.push_back(t);
+            work.push_back(cps[l] * (double)t.count);
+        }
+    }
+    // segments
+    std::vector<size_t> seg = {0};
+    double acc = 0;
+    for (size_t t = 0; t < tasks.size(); ++t) {
+        if (acc > 0 && acc + work[t] > cap) { seg.push_back(t); acc = 0; }
+        acc += work[t];
+    }
+    seg.push_back(tasks.size());
+    size_t max_seg = 0;
+    for (size_t k = 0; k + 1 < seg.size(); ++k) max_seg = std::max(max_seg, seg[k + 1] - seg[k]);
+    // buffers; the graph is captured again when any of them moved
+    const uint64_t stride = 256ull * nobs * 2;
+    const void* before[6] = {ctx->pr_levels.p, ctx->pr_tasks.p, ctx->pr_ntasks.p, ctx->pr_head.p, ctx->pr_task_mom.p,
+                             ctx->pr_scratch.p};
+    int rc;
+    if ((rc = ctx->pr_levels.ensure(sizeof(dk::RoundLevel) * DK_MAX_LEVELS))) return rc;
+    if ((rc = ctx->pr_tasks.ensure(sizeof(dk::RoundTask) * max_seg))) return rc;
+    if ((rc = ctx->pr_ntasks.ensure(sizeof(uint32_t)))) return rc;
+    if ((rc = ctx->pr_head.ensure(sizeof(uint32_t)))) return rc;
+    if ((rc = ctx->pr_task_mom.ensure(sizeof(double) * 2 * nmom * max_seg))) return rc;
+    if ((rc = ctx->pr_scratch.ensure(sizeof(double) * stride * grid))) return rc;
+    const size_t host_bytes = sizeof(dk::RoundLevel) * DK_MAX_LEVELS + sizeof(dk::RoundTask) * max_seg + 64 +
+                              sizeof(double) * 2 * nmom * max_seg;
+    if (host_bytes > ctx->pr_host_bytes) {
+        if (ctx->pr_host) { (void)hipHostFree(ctx->pr_host); ctx->pr_host = nullptr; ctx->pr_host_bytes = 0; }
+        if (hipHostMalloc(&ctx->pr_host, host_bytes, hipHostMallocDefault) != hipSuccess)
+            return fail(DK_ENOMEM, "hipHostMalloc(%zu) failed", host_bytes);
+        ctx->pr_host_bytes = host_bytes;
+    }
+    const void* after[6] = {ctx->pr_levels.p, ctx->pr_tasks.p, ctx->pr_ntasks.p, ctx->pr_head.p, ctx->pr_task_mom.p,
+                            ctx->pr_scratch.p};
+    bool moved = std::memcmp(before, after, sizeof(before)) != 0;
+    if (!ctx->pr_exec || moved || ctx->pr_flux != p->flux || ctx->pr_args.n_obs != nobs) {
+        if (ctx->pr_exec) { (void)hipGraphExecDestroy(ctx->pr_exec); ctx->pr_exec = nullptr; }
+        if (ctx->pr_graph) { (void)hipGraphDestroy(ctx->pr_graph); ctx->pr_graph = nullptr; }
+        dk::RoundArgs P{};
+        P.levels = (const dk::RoundLevel*)ctx->pr_levels.p;
+        P.tasks = (const dk::RoundTask*)ctx->pr_tasks.p;
+        P.ntasks = (const uint32_t*)ctx->pr_ntasks.p;
+        P.head = (uint32_t*)ctx->pr_head.p;
+        P.task_mom = (double*)ctx->pr_task_mom.p;
+        P.scratch = (double*)ctx->pr_scratch.p;
+        P.scratch_stride = stride;
+        P.n_obs = nobs;
+        if (!ctx->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+        const hipError_t el = dk::launch_round(P, p->flux, grid, ctx->cap_stream);
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &g);
+        if (el != hipSuccess) { if (g) (void)hipGraphDestroy(g); return fail(DK_EDEVICE, "round launch: %s", hipGetErrorString(el)); }
+        if (ec != hipSuccess) return fail(DK_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+        ctx->pr_graph = g;
+        HIP_TRY(hipGraphInstantiate(&ctx->pr_exec, g, nullptr, nullptr, 0));
+        ctx->pr_args = P;
+        ctx->pr_flux = p->flux;
+    }
+    char* hb = (char*)ctx->pr_host;
+    dk::RoundLevel* h_lv = (dk::RoundLevel*)hb;
+    dk::RoundTask* h_tasks = (dk::RoundTask*)(hb + sizeof(dk::RoundLevel) * DK_MAX_LEVELS);
+    uint32_t* h_nt = (uint32_t*)((char*)h_tasks + sizeof(dk::RoundTask) * max_seg);
+    double* h_mom = (double*)((char*)h_nt + 64);
+    for (int l = 0; l <= L; ++l) h_lv[l] = lv[l];
+    HIP_TRY(hipMemcpyAsync(ctx->pr_levels.p, h_lv, sizeof(dk::RoundLevel) * (L + 1), hipMemcpyHostToDevice, s));
+    const bool log = std::getenv("DK_LOG") != nullptr;
+    KStat& rs = ctx->stats[std::make_pair(-1, 0)];
+    rs.rows = 8;
+    for (size_t k = 0; k + 1 < seg.size(); ++k) {
+        const size_t t0 = seg[k], t1 = seg[k + 1], nt = t1 - t0;
+        std::memcpy(h_tasks, &tasks[t0], sizeof(dk::RoundTask) * nt);
+        *h_nt = (uint32_t)nt;
+        HIP_TRY(hipMemcpyAsync(ctx->pr_tasks.p, h_tasks, sizeof(dk::RoundTask) * nt, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(ctx->pr_ntasks.p, h_nt, sizeof(uint32_t), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipEventRecord(ctx->pr_t0, s));
+        HIP_TRY(hipGraphLaunch(ctx->pr_exec, s));
+        HIP_TRY(hipEventRecord(ctx->pr_t1, s));
+        HIP_TRY(hipMemcpyAsync(h_mom, ctx->pr_task_mom.p, sizeof(double) * 2 * nmom * nt, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ctx->pr_t0, ctx->pr_t1));
+        double seg_cells = 0;
+        uint64_t seg_samples = 0;
+        for (size_t t = t0; t < t1; ++t) {
+            const dk::RoundTask& T = tasks[t];
+            for (int j = 0; j < nobs; ++j)
+                merge_moments(sums[(size_t)T.level * nobs + j], &h_mom[((t - t0) * nobs + j) * DK_NMOM * 2], T.count);
+            KStat& st = ctx->stats[std::make_pair((int)T.level, T.level >= 1 ? 1 : 0)];
+            st.samples += T.count;
+            st.cells += work[t];
+            st.rows = 8;
+            seg_cells += work[t];
+            seg_samples += T.count;
+        }
+        rs.launches += 1;
+        rs.samples += seg_samples;
+        rs.cells += seg_cells;
+        rs.ms += ms;
+        ctx->round_ms += ms;
+        ctx->round_graphs += 1;
+        if (cell_updates) *cell_updates += seg_cells;
+        if (log) {
+            std::fprintf(stderr, "[dk] persistent round segment %zu/%zu: %zu tasks, %.3g cell updates, %.1f ms (%.3g /s)\n",
+                         k + 1, seg.size() - 1, nt, seg_cells, ms, seg_cells / (ms * 1e-3));
+            std::fflush(stderr);
+        }
+    }
+    for (int l = 0; l <= L; ++l)
+        for (int j = 0; j < nobs && count[l] > 0; ++j)
+            for (int m = 0; m < DK_NMOM; ++m)
+                if (!std::isfinite(mom_value(sums[(size_t)l * nobs + j], m)))
+                    return fail(DK_ENUMERIC, "non-finite sample values on level %d", l);
     return DK_OK;
 }
 
@@ -1018,11 +1220,11 @@ int run_cv_level(dk_context* ctx, const dk_problem* p, int level, uint64_t first
 }
 
 struct GpuSampler {
-    dk_context* ctx;
-    const dk_problem* p;
-    hipStream_t s;
-    uint32_t tag;
-    bool plain_mc;
+    dk_context* ctx = nullptr;
+    const dk_problem* p = nullptr;
+    hipStream_t s = nullptr;
+    uint32_t tag = DK_TAG_MLMC;
+    bool plain_mc = false;
     std::vector<dk_moments> mom;   // [levels][n_obs]
     std::vector<dk_moments> tmp;
     double cell_updates = 0;
@@ -1030,7 +1232,8 @@ struct GpuSampler {
     uint32_t cv_mask = 0;
     int cv_ratio = 4;
     std::vector<dk_moments> zmom;       // [levels] moments of the control-variate samples
-    int round_mode = 0;                 // 0: level after level, 1: concurrent streams, 2: hipGraph per round
+    int round_mode = 0;                 // 0: level after level, 1: concurrent streams, 2: hipGraph per round,
+                                        // 3: persistent round kernel (graph replayed per segment)
 };
 
 int gpu_sample(void* user, int32_t level, uint64_t first, uint64_t count, double* sums)
@@ -1083,7 +1286,8 @@ int gpu_round(void* user, int L, const uint64_t* first, const uint64_t* count, d
         const int nf = G.p->n0 << l;
         const bool cv = l >= 1 && G.cv_params && ((G.cv_mask >> l) & 1u);
         const bool streamed = !dk::level_supported(nf) || (G.ctx->force_stream && dk::stream_supported(nf));
-        if ((cv || streamed || G.plain_mc) && count[l] > 0) {
+        const bool outside = G.round_mode == 3 && G.p->precision == DK_PREC_F32 && !round_eligible(G.p, l, G.ctx->force_stream);
+        if ((cv || streamed || outside || G.plain_mc) && count[l] > 0) {
             double s2[2] = {0, 0};
             const int rc = gpu_sample(user, l, first[l], count[l], s2);
             if (rc < 0) return rc;
@@ -1093,7 +1297,11 @@ int gpu_round(void* user, int L, const uint64_t* first, const uint64_t* count, d
         }
     }
     std::vector<dk_moments> rs((size_t)(L + 1) * nobs);
-    const int rc = run_round(G.ctx, G.p, L, first, cnt.data(), G.tag, G.round_mode, rs, G.s, &G.cell_updates);
+    // persistent rounds need FP32 states; FP64 problems take the concurrent-stream round instead
+    const bool persistent = G.round_mode == 3 && G.p->precision == DK_PREC_F32 && nobs <= dk::round_max_obs();
+    const int rc = persistent ? run_round_persistent(G.ctx, G.p, L, first, cnt.data(), G.tag, rs, G.s, &G.cell_updates)
+                              : run_round(G.ctx, G.p, L, first, cnt.data(), G.tag, G.round_mode == 3 ? 1 : G.round_mode, rs, G.s,
+                                          &G.cell_updates);
     if (rc < 0) return rc;
     for (int l = 0; l <= L; ++l) {
         if (cnt[l] == 0) continue;
@@ -1340,6 +1548,11 @@ void dk_context_destroy(dk_context* ctx)
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->rnd_t0) (void)hipEventDestroy(ctx->rnd_t0);
     if (ctx->rnd_t1) (void)hipEventDestroy(ctx->rnd_t1);
+    if (ctx->pr_exec) (void)hipGraphExecDestroy(ctx->pr_exec);
+    if (ctx->pr_graph) (void)hipGraphDestroy(ctx->pr_graph);
+    if (ctx->pr_t0) (void)hipEventDestroy(ctx->pr_t0);
+    if (ctx->pr_t1) (void)hipEventDestroy(ctx->pr_t1);
+    if (ctx->pr_host) (void)hipHostFree(ctx->pr_host);
     delete ctx;
 }
 
@@ -1412,6 +1625,14 @@ int dk_heat_steps(dk_context* ctx, int32_t n, int32_t batch, int32_t steps, doub
     if (kernel_ms) *kernel_ms = ms;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    return DK_OK;
+}
+
+int dk_context_set_launch_cap(dk_context* ctx, double cells)
+{
+    if (!ctx) return fail(DK_EINVAL, "context is NULL");
+    if (!(cells >= 0)) return fail(DK_EINVAL, "cells must be >= 0");
+    ctx->max_launch_cells = cells == 0 ? kMaxCellsPerLaunch : std::max(cells, 1e6);
     return DK_OK;
 }
 
@@ -1502,6 +1723,42 @@ int dk_alg1_host(double eps, int32_t L_max, const double* cost, const dk_mlmc_op
     return alg1_core(eps, L_max, cost, o, sampler, user, out);
 }
 
+int dk_mlmc_round(dk_context* ctx, const dk_problem* problem, int32_t L, const uint64_t* first, const uint64_t* count,
+                  uint32_t tag, int32_t round_mode, dk_moments* sums_out, void* stream)
+{
+    if (!ctx) return fail(DK_EINVAL, "context is NULL");
+    if (!first || !count || !sums_out) return fail(DK_EINVAL, "NULL argument");
+    int rc = validate(problem);
+    if (rc) return rc;
+    if (L < 0 || L >= problem->levels) return fail(DK_EINVAL, "L must be in [0, levels)");
+    if (round_mode < 0 || round_mode > 3) return fail(DK_EINVAL, "round_mode must be 0, 1, 2 or 3");
+    if (tag > 255) return fail(DK_EINVAL, "tag must be < 256");
+    for (int l = 0; l <= L; ++l)
+        if (count[l] > 0 && (first[l] >> 48) + ((first[l] + count[l] - 1) >> 48) != 0)
+            return fail(DK_EINVAL, "sample indices must stay below 2^48");
+    HIP_TRY(hipSetDevice(ctx->device));
+    const int nobs = problem->n_obs;
+    GpuSampler G;
+    G.ctx = ctx;
+    G.p = problem;
+    G.s = (hipStream_t)stream;
+    G.mom.assign((size_t)problem->levels * nobs, dk_moments{});
+    G.zmom.assign(problem->levels, dk_moments{});
+    G.tag = tag;
+    G.plain_mc = false;
+    G.round_mode = round_mode;
+    std::vector<double> prim(2 * (L + 1), 0.0);
+    if (round_mode == 0) {
+        for (int l = 0; l <= L; ++l)
+            if (count[l] > 0 && (rc = gpu_sample(&G, l, first[l], count[l], &prim[2 * l])) < 0) return rc;
+    } else if ((rc = gpu_round(&G, L, first, count, prim.data())) < 0) {
+        return rc;
+    }
+    for (int l = 0; l <= L; ++l)
+        for (int j = 0; j < nobs; ++j) sums_out[(size_t)l * nobs + j] = G.mom[(size_t)l * nobs + j];
+    return DK_OK;
+}
+
 int dk_mlmc_estimate(dk_context* ctx, const dk_problem* problem, double eps, const dk_mlmc_opts* opts,
                      dk_mlmc_result* out, dk_moments* level_moments, void* stream)
 {
@@ -1544,7 +1801,7 @@ int dk_mlmc_estimate(dk_context* ctx, const dk_problem* problem, double eps, con
             if ((G.cv_mask >> l) & 1u) cost[l] += G.cv_ratio * level_cost(problem, s0, l - 1, false);
         }
         G.round_mode = o.round_mode;
-        if (o.round_mode < 0 || o.round_mode > 2) return fail(DK_EINVAL, "round_mode must be 0, 1 or 2");
+        if (o.round_mode < 0 || o.round_mode > 3) return fail(DK_EINVAL, "round_mode must be 0, 1, 2 or 3");
         rc = alg1_core(eps, problem->levels - 1, cost.data(), o, gpu_sample, &G, out,
                        o.round_mode > 0 ? gpu_round : nullptr);
         if (rc < 0) return rc;

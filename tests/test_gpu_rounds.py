@@ -32,3 +32,98 @@ def test_round_modes_identical(name, problem, eps):
         assert r["estimate"] == res[0]["estimate"]
         assert r["Yhat"] == res[0]["Yhat"] and r["Vhat"] == res[0]["Vhat"]
     assert len(res[0]["estimate"]) == len(problem.obs)
+
+
+def exact_moments(ps):
+    """Exactly rounded sums (math.fsum) of the six moments of per-sample (P_f, P_c) values,
+    and the sums of absolute values that bound the compensated sums' error."""
+    import math
+    import numpy as np
+    pf, pc = ps[:, 0], ps[:, 1]
+    y = pf - pc
+    vals = [y, y * y, pf, pf * pf, pc, pc * pc]
+    return np.array([math.fsum(v) for v in vals]), np.array([math.fsum(np.abs(v)) for v in vals])
+
+
+def per_sample(problem, level, first, count, ctx):
+    _, ps = dk.level_pair(problem, level, first, count, per_sample=True, ctx=ctx)
+    return ps.cpu().numpy()
+
+
+@pytest.mark.parametrize("name,problem,first,count,cap", [
+    # ragged counts on every level, one launch per round
+    ("config2", W.config2(N=1e4).with_(seed=11), [13, 5, 0, 2, 1], [1000 + 3, 517, 130, 37, 5], 0),
+    # 29 observables, a count of 1, and a launch cap that cuts the round into many segments
+    # (graph replays)
+    ("config3", W.config3(N=1e3).with_(levels=5, seed=5), [0, 7, 3, 0, 9], [700, 1, 66, 20, 3], 1e8),
+])
+def test_persistent_round_sums_match_per_sample_values(name, problem, first, count, cap):
+    """round_mode 3 runs every sample with the same code as the per-level kernel (8 rows per lane)
+    and sums moments per task with Neumaier's method: its sums equal the exactly rounded sums of
+    the per-level kernel's per-sample values to within 1e-13 of the sum of magnitudes."""
+    ctx = dk.Context(0)
+    for n in (8, 16, 32, 64, 128):
+        ctx.set_shape(n, 0)                    # 8 rows per lane on the per-level path too
+    if cap:
+        ctx.set_launch_cap(cap)
+    L = len(count) - 1
+    print(f"[gpu] {name}: persistent round, counts {count}", flush=True)
+    got = dk.round_sums(problem, L, first, count, round_mode=3, ctx=ctx)
+    for l in range(L + 1):
+        print(f"[gpu] {name}: level {l} per-sample reference", flush=True)
+        ps = per_sample(problem, l, first[l], count[l], ctx)
+        for j in range(len(problem.obs)):
+            ex, mag = exact_moments(ps[:, j, :])
+            m = got[l][j]
+            assert m.count == count[l]
+            assert (abs(m.sums - ex) <= 1e-13 * mag + 1e-300).all(), (l, j, m.sums, ex)
+    stats = {(s["level"], s["coupled"]): s for s in ctx.stats()}
+    rk = stats[(-1, 0)]
+    assert rk["samples"] == sum(count)
+    assert rk["launches"] >= (2 if cap else 1)
+    ctx.close()
+
+
+def test_persistent_round_empty_levels_and_modes_agree():
+    """Levels with no samples are skipped; the other modes run the same samples (same per-sample
+    values with 8 rows per lane), so all four modes agree to rounding."""
+    p = W.config2(N=1e4).with_(seed=2)
+    first, count = [0, 0, 100, 0, 4], [512, 0, 64, 0, 3]
+    res = {}
+    for mode in (0, 1, 2, 3):
+        print(f"[gpu] round_sums mode={mode}", flush=True)
+        ctx = dk.Context(0)
+        for n in (8, 16, 32, 64, 128):
+            ctx.set_shape(n, 0)
+        res[mode] = dk.round_sums(p, 4, first, count, round_mode=mode, ctx=ctx)
+        ctx.close()
+    for l in range(5):
+        for mode in (1, 2, 3):
+            a, b = res[mode][l][0], res[0][l][0]
+            assert a.count == b.count == count[l]
+            scale = max(1.0, float(abs(b.sums).max()))
+            assert (abs(a.sums - b.sums) <= 1e-12 * scale).all(), (mode, l, a.sums, b.sums)
+
+
+def test_persistent_estimate_agrees_with_level_path():
+    """Algorithm 1 with persistent rounds on config 3 (29 observables, all six levels from the
+    first round; the streamed 256 x 256 level joins each round through the level path) agrees
+    with the level-by-level run."""
+    p = W.config3(N=1e5).with_(levels=6, seed=3)
+    out = {}
+    for mode in (0, 3):
+        print(f"[gpu] config3 estimate round_mode={mode}", flush=True)
+        ctx = dk.Context(0)
+        for n in (8, 16, 32, 64, 128):
+            ctx.set_shape(n, 0)
+        out[mode] = dk.estimate(p, 1e-2, ctx=ctx, round_mode=mode, L_start=5, m_pilot=200)
+        ctx.close()
+    a, b = out[3], out[0]
+    assert a["L"] == b["L"]
+    if a["M"] == b["M"]:
+        for x, y in zip(a["estimate"], b["estimate"]):
+            assert abs(x - y) <= 1e-10 * max(1.0, abs(y))
+    else:                                      # a sample count rounded the other way
+        import math
+        for x, y, v in zip(a["estimate"], b["estimate"], b["var_est"]):
+            assert abs(x - y) <= 4.5 * math.sqrt(2 * v) + 1e-12
