@@ -151,7 +151,18 @@ struct RowLoop {
 //   halo: this sample's LDS area, [G][2 (top,bottom)][2 (rho, w1)][NN]
 //   g, G: row group of the lane and number of groups; cl: column lane; NN: grid width
 // ---------------------------------------------------------------------------------------
-template <typename Real, int R, int C, int FLUX, bool NOISE, bool COMP, bool ONE_BARRIER, class Noise>
+// Synchronisation of the lanes of one sample around the LDS halo exchange.  A sample spread over
+// several wavefronts needs the block barrier.  A sample inside one wavefront does not: the LDS
+// serves one wavefront's requests in issue order, so it is enough that the compiler keeps this
+// wavefront's LDS accesses on their side of this point.
+template <bool WAVE_LOCAL>
+__device__ __forceinline__ void sample_sync()
+{
+    if constexpr (WAVE_LOCAL) asm volatile("" ::: "memory");
+    else __syncthreads();
+}
+
+template <typename Real, int R, int C, int FLUX, bool NOISE, bool COMP, bool ONE_BARRIER, bool WAVE_LOCAL, class Noise>
 __device__ __forceinline__ void tile_step(Real (&rho)[R][C], Real (&cmp)[R][C], Noise& noise, const Real a, const Real kappa,
                                           Real* __restrict__ halo, const int g, const int G, const int cl,
                                           const int NN, const int addr_l, const int addr_r)
@@ -175,7 +186,7 @@ __device__ __forceinline__ void tile_step(Real (&rho)[R][C], Real (&cmp)[R][C], 
             bot[NN + c] = (R > 1) ? w1_last[c] : w1_first[c];
         }
     }
-    __syncthreads();
+    sample_sync<WAVE_LOCAL>();
     const int gu = g == 0 ? G - 1 : g - 1;
     const int gd = g == G - 1 ? 0 : g + 1;
     const Real* above = halo + (gu * 2 + 1) * 2 * NN + C * cl;
@@ -192,7 +203,7 @@ __device__ __forceinline__ void tile_step(Real (&rho)[R][C], Real (&cmp)[R][C], 
     }
     // With a double-buffered halo (alternating by step) the next step writes the other buffer,
     // and its barrier orders those writes after every lane's reads of this one.
-    if constexpr (!ONE_BARRIER) __syncthreads();
+    if constexpr (!ONE_BARRIER) sample_sync<WAVE_LOCAL>();
 
     Real rprev[C];     // old density of row i-1
     Real F1prev[C];    // y-flux of row i-1 (central) / of edge (i-1, i) (staggered)
@@ -376,6 +387,7 @@ __device__ __forceinline__ void level_body(const LevelArgs& A, uint64_t local0, 
     static_assert(TS <= 64 || TS % 64 == 0, "sample lanes");
 
     constexpr int HALO = halo_elems<NF, R, PAIR>();
+    constexpr bool WL = TS <= 64;     // the sample's lanes lie inside one wavefront
 
     const int sw = tid / TS;
     const int t = tid % TS;
@@ -431,11 +443,11 @@ __device__ __forceinline__ void level_body(const LevelArgs& A, uint64_t local0, 
             FineNoise<Real, R, C, PAIR> fn{key, (uint32_t)m, (uint32_t)(col0 / 2 + row0 * (NF / 2)),
                                            (uint32_t)(NF / 2), PAIR ? (Real(*)[C / 2 > 0 ? C / 2 : 1][2])Z : nullptr,
                                            pend};
-            tile_step<Real, R, C, FLUX, true, COMP, true>(rho, rho_cmp, fn, a, kf, my_halo + (m & 1) * G * 4 * NF, g, G,
+            tile_step<Real, R, C, FLUX, true, COMP, true, WL>(rho, rho_cmp, fn, a, kf, my_halo + (m & 1) * G * 4 * NF, g, G,
                                                           cl, NF, addr_l, addr_r);
         } else {
             NoNoise<Real, C> nn;
-            tile_step<Real, R, C, FLUX, false, false, true>(rho, rho_cmp, nn, a, Real(0), my_halo + (m & 1) * G * 4 * NF, g,
+            tile_step<Real, R, C, FLUX, false, false, true, WL>(rho, rho_cmp, nn, a, Real(0), my_halo + (m & 1) * G * 4 * NF, g,
                                                             G, cl, NF, addr_l, addr_r);
         }
     };
@@ -446,7 +458,7 @@ __device__ __forceinline__ void level_body(const LevelArgs& A, uint64_t local0, 
 #pragma unroll 1
             for (int j = 0; j < 4; ++j) fine_step(4 * mc + j);
             CoarseNoise<Real, RC, CCc> cn{Z};
-            tile_step<Real, RC, CCc, FLUX, NOISE, COMP, false>(rhoc, rhoc_cmp, cn, a, kc, my_halo + 2 * G * 4 * NF, g, G,
+            tile_step<Real, RC, CCc, FLUX, NOISE, COMP, false, WL>(rhoc, rhoc_cmp, cn, a, kc, my_halo + 2 * G * 4 * NF, g, G,
                                                                  cl, NC, addr_l, addr_r);
 #pragma unroll
             for (int i = 0; i < RC; ++i)
