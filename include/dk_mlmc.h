@@ -317,6 +317,19 @@ int dk_context_reset(dk_context* ctx, int32_t drop_tables);
 int dk_context_set_shape(dk_context* ctx, int32_t n, int32_t variant);
 int dk_shape_rows(int32_t n, int32_t variant);
 
+/* The autotuner's tile-shape choices of the context (and those loaded) as JSON text:
+ *   {"format": "dk-tile-shapes-1", "arch": "gfx950",
+ *    "shapes": [{"n": 128, "pair": 1, "flux": 0, "rows": 8}, ...]}
+ * Writes at most cap bytes including the terminating NUL into buf (buf may be NULL when cap is
+ * 0) and returns the text's full length without the NUL, or a negative error code. */
+int dk_context_tuning_json(dk_context* ctx, char* buf, uint64_t cap);
+/* Loads choices in that format; listed shapes replace the context's choices and are used
+ * without timing.  DK_EINVAL if the text lacks the format tag, names another architecture or
+ * lists a row count that no compiled shape of that grid has.  With the environment variable
+ * DK_TUNE_CACHE set to a file path, every context loads that file when it is created (if it
+ * exists and is valid) and rewrites it whenever the autotuner makes a new choice. */
+int dk_context_load_tuning_json(dk_context* ctx, const char* json);
+
 /* Grids larger than 128 x 128 (multiples of 64) run on the streaming kernel: the FP32 state
  * stays in HBM (double-buffered), each launch advances 64 x 64 tiles with a 4-cell halo by 4
  * fine steps (one coarse step for pairs), regenerating the halo's noise.  Its fields are

@@ -134,6 +134,17 @@ class Context:
         """Force tile-shape variant `variant` for grid size n (-1: automatic)."""
         _check(self.lib.dk_context_set_shape(self.h, n, variant))
 
+    def tuning_json(self) -> str:
+        """The autotuner's tile-shape choices as JSON text."""
+        n = _check(self.lib.dk_context_tuning_json(self.h, None, 0))
+        buf = C.create_string_buffer(n + 1)
+        _check(self.lib.dk_context_tuning_json(self.h, buf, n + 1))
+        return buf.value.decode()
+
+    def load_tuning_json(self, text: str):
+        """Use tile-shape choices from JSON text (as written by tuning_json) without timing."""
+        _check(self.lib.dk_context_load_tuning_json(self.h, text.encode()))
+
     def set_launch_cap(self, cells: float):
         """Largest work of one sampling launch in cell updates (0 = default 2e12)."""
         _check(self.lib.dk_context_set_launch_cap(self.h, float(cells)))

@@ -16,7 +16,10 @@
 
 #include "dk_cnn.h"
 #include "dk_internal.h"
+#include <fstream>
 #include <random>
+#include <regex>
+#include <sstream>
 
 namespace {
 
@@ -364,6 +367,75 @@ uint64_t chunk_size(int n_obs, double cells_per_sample, double max_cells)
     return c;
 }
 
+// ------------------------------------------------------------------------------------------
+// Tile-shape choices as JSON text:
+//   {"format": "dk-tile-shapes-1", "arch": "gfx950",
+//    "shapes": [{"n": 128, "pair": 1, "flux": 0, "rows": 8}, ...]}
+// ------------------------------------------------------------------------------------------
+std::string device_arch(int device)
+{
+    hipDeviceProp_t pr;
+    if (hipGetDeviceProperties(&pr, device) != hipSuccess) return "unknown";
+    std::string a = pr.gcnArchName;
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+std::string tuning_json(const dk_context* ctx)
+{
+    std::ostringstream o;
+    o << "{\"format\": \"dk-tile-shapes-1\", \"arch\": \"" << device_arch(ctx->device) << "\", \"shapes\": [";
+    bool first = true;
+    for (const auto& kv : ctx->tuned) {
+        const int nf = (int)(kv.first >> 8), pair = (int)((kv.first >> 4) & 0xF), flux = (int)(kv.first & 0xF);
+        o << (first ? "" : ", ") << "{\"n\": " << nf << ", \"pair\": " << pair << ", \"flux\": " << flux
+          << ", \"rows\": " << dk::shape_rows(nf, kv.second) << "}";
+        first = false;
+    }
+    o << "]}";
+    return o.str();
+}
+
+int load_tuning_json(dk_context* ctx, const std::string& text)
+{
+    static const std::regex fmt("\"format\"\\s*:\\s*\"dk-tile-shapes-1\"");
+    static const std::regex arch("\"arch\"\\s*:\\s*\"([^\"]*)\"");
+    static const std::regex entry("\\{\\s*\"n\"\\s*:\\s*(\\d+)\\s*,\\s*\"pair\"\\s*:\\s*(\\d+)\\s*,\\s*\"flux\"\\s*:\\s*(\\d+)"
+                                  "\\s*,\\s*\"rows\"\\s*:\\s*(\\d+)\\s*\\}");
+    if (!std::regex_search(text, fmt)) return fail(DK_EINVAL, "tuning JSON: missing \"format\": \"dk-tile-shapes-1\"");
+    std::smatch m;
+    if (!std::regex_search(text, m, arch)) return fail(DK_EINVAL, "tuning JSON: missing \"arch\"");
+    const std::string dev = device_arch(ctx->device);
+    if (m[1].str() != dev) return fail(DK_EINVAL, "tuning JSON is for %s, the device is %s", m[1].str().c_str(), dev.c_str());
+    std::map<long, int> got;
+    for (auto it = std::sregex_iterator(text.begin(), text.end(), entry); it != std::sregex_iterator(); ++it) {
+        const int nf = std::stoi((*it)[1]), pair = std::stoi((*it)[2]), flux = std::stoi((*it)[3]);
+        const int rows = std::stoi((*it)[4]);
+        if (pair > 1 || (flux != DK_FLUX_CENTRAL && flux != DK_FLUX_STAGGERED))
+            return fail(DK_EINVAL, "tuning JSON: bad entry for n = %d", nf);
+        int v = 0;
+        while (dk::shape_rows(nf, v) > 0 && dk::shape_rows(nf, v) != rows) ++v;
+        if (dk::shape_rows(nf, v) == 0) return fail(DK_EINVAL, "tuning JSON: no %d-row shape for n = %d", rows, nf);
+        got[((long)nf << 8) | ((long)pair << 4) | (long)flux] = v;
+    }
+    for (const auto& kv : got) ctx->tuned[kv.first] = kv.second;
+    return DK_OK;
+}
+
+// DK_TUNE_CACHE: the file the context loads when created and rewrites after every new choice
+void save_tuning_cache(const dk_context* ctx)
+{
+    const char* path = std::getenv("DK_TUNE_CACHE");
+    if (!path || !*path) return;
+    const std::string tmp = std::string(path) + ".tmp";
+    {
+        std::ofstream f(tmp);
+        if (!f) return;
+        f << tuning_json(ctx) << "\n";
+    }
+    std::rename(tmp.c_str(), path);
+}
+
 // Tile-shape choice for the FP32 noisy kernels: a forced variant, a cached choice, or the
 // fastest variant on a short tuning batch (same tables, at most 256 fine steps, samples from
 // the requested range; the outputs are discarded).  Small jobs use the default shape.
@@ -385,7 +457,7 @@ int choose_shape(dk_context* ctx, const dk_problem* p, bool pair, const dk::Leve
     if ((double)count * cells_per_sample < 1e11) return DK_OK;
     int nvar = 0;
     while (dk::shape_rows(nf, nvar) > 0) ++nvar;
-    if (nvar < 2) { ctx->tuned[key] = 0; return DK_OK; }
+    if (nvar < 2) { ctx->tuned[key] = 0; save_tuning_cache(ctx); return DK_OK; }
     dk::LevelArgs T = A;
     T.count = std::min<uint64_t>(count, nf <= 32 ? 8192 : (nf == 64 ? 2048 : 1024));
     T.steps = std::min(A.steps, 256);
@@ -416,6 +488,7 @@ int choose_shape(dk_context* ctx, const dk_problem* p, bool pair, const dk::Leve
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     ctx->tuned[key] = bestv;
+    save_tuning_cache(ctx);
     if (std::getenv("DK_LOG")) {
         std::fprintf(stderr, "[dk] tuned n=%d pair=%d flux=%d:", nf, (int)pair, p->flux);
         for (auto& kv : ctx->tune_log) std::fprintf(stderr, " R=%d %.3f ms", dk::shape_rows(nf, kv.first), kv.second);
@@ -1531,8 +1604,36 @@ int dk_context_create(dk_context** out, int device)
     dk_context* c = new (std::nothrow) dk_context();
     if (!c) return fail(DK_ENOMEM, "context allocation failed");
     c->device = device;
+    if (const char* path = std::getenv("DK_TUNE_CACHE")) {
+        std::ifstream f(path);
+        if (f) {
+            std::stringstream ss;
+            ss << f.rdbuf();
+            if (load_tuning_json(c, ss.str()) != DK_OK && std::getenv("DK_LOG"))
+                std::fprintf(stderr, "[dk] DK_TUNE_CACHE %s ignored: %s\n", path, dk_last_error());
+        }
+    }
     *out = c;
     return DK_OK;
+}
+
+int dk_context_tuning_json(dk_context* ctx, char* buf, uint64_t cap)
+{
+    if (!ctx) return fail(DK_EINVAL, "context is NULL");
+    if (cap > 0 && !buf) return fail(DK_EINVAL, "buf is NULL");
+    const std::string t = tuning_json(ctx);
+    if (cap > 0) {
+        const size_t n = std::min<size_t>(t.size(), (size_t)cap - 1);
+        std::memcpy(buf, t.data(), n);
+        buf[n] = 0;
+    }
+    return (int)t.size();
+}
+
+int dk_context_load_tuning_json(dk_context* ctx, const char* json)
+{
+    if (!ctx || !json) return fail(DK_EINVAL, "NULL argument");
+    return load_tuning_json(ctx, std::string(json));
 }
 
 void dk_context_destroy(dk_context* ctx)

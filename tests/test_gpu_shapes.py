@@ -45,3 +45,45 @@ def test_shape_variants_agree(level, flux):
         v += 1
     assert v >= 2
     ctx.close()
+
+
+def test_tuning_choices_round_trip_through_json(tmp_path, monkeypatch, capfd):
+    """The autotuner's choice is exported as JSON, a fresh context that loads the text uses it
+    without timing, the DK_TUNE_CACHE file is written and read, and bad text is rejected."""
+    import json
+    monkeypatch.setenv("DK_LOG", "1")
+    cache = tmp_path / "shapes.json"
+    monkeypatch.setenv("DK_TUNE_CACHE", str(cache))
+    p = W.config2(N=1e4)
+    ctx = dk.Context(0)
+    dk.level_pair(p, 4, 0, 720, ctx=ctx)          # 1.03e11 cell updates: large enough to be tuned
+    assert "tuned n=128" in capfd.readouterr().err
+    text = ctx.tuning_json()
+    j = json.loads(text)
+    entry = [e for e in j["shapes"] if e["n"] == 128 and e["pair"] == 1 and e["flux"] == p.flux]
+    assert j["format"] == "dk-tile-shapes-1" and j["arch"].startswith("gfx") and len(entry) == 1
+    rows = entry[0]["rows"]
+    assert rows in (8, 16)
+    ctx.close()
+    assert json.loads(cache.read_text()) == j      # DK_TUNE_CACHE rewritten after the choice
+
+    ctx2 = dk.Context(0)                           # loads DK_TUNE_CACHE when created
+    assert json.loads(ctx2.tuning_json()) == j
+    dk.level_pair(p, 4, 0, 720, ctx=ctx2)
+    assert "tuned n=128" not in capfd.readouterr().err
+    st = [s for s in ctx2.stats() if s["level"] == 4]
+    assert st and st[0]["rows"] == rows
+    with pytest.raises(dk.DKError):
+        ctx2.load_tuning_json(text.replace(j["arch"], "gfx000"))
+    with pytest.raises(dk.DKError):
+        ctx2.load_tuning_json(text.replace(f'"rows": {rows}', '"rows": 3'))
+    with pytest.raises(dk.DKError):
+        ctx2.load_tuning_json("{}")
+    ctx2.close()
+
+    monkeypatch.delenv("DK_TUNE_CACHE")
+    ctx3 = dk.Context(0)
+    assert json.loads(ctx3.tuning_json())["shapes"] == []
+    ctx3.load_tuning_json(text)
+    assert json.loads(ctx3.tuning_json()) == j
+    ctx3.close()
