@@ -26,10 +26,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLMC wall-time to RMSE 1e-3 (plain vs learned CV); cell-updates/s and HBM %"
 
-# Algorithmic vector-ALU operations per fine cell update of a coupled pair (see the design doc,
-# "Measurement"): half a Philox4x32-10 call (40), one binary32 Box--Muller pair (60), the
-# explicit EM update with central flux and compensated increment (18), the NN restriction
-# and the amortised coarse step (3).
+# Algorithmic vector-ALU operations per fine cell update of a coupled pair: half a
+# Philox4x32-10 call (40), one binary32 Box--Muller pair (60), the explicit EM update with
+# central flux and compensated increment (18), the NN restriction and the amortised coarse
+# step (3).
 OPS_PER_CELL_UPDATE = 121.0
 # MI355X vector FP32 rate: 157.3 TFLOP/s counts an FMA as 2 flops, i.e. 78.6e12 32-bit
 # vector lane-operations per second (256 CUs x 128 lanes x 2.4 GHz).
@@ -47,6 +47,12 @@ def parse():
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle sampling")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 256 MiB buffer 4 times (reference for HBM byte counters)")
+    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4", "config5"],
+                    help="config2 (default): the bench line; the others print a report line: config3 "
+                         "low-density MLMC with persistent rounds, config4 learned control variate, "
+                         "config5 streaming-kernel throughput at 256^2..1024^2")
+    ap.add_argument("--N", type=float, default=None, help="particle number (config3: 1e5, config5: 1e6)")
+    ap.add_argument("--samples", type=int, default=32, help="config5: finest-level pairs to time")
     return ap.parse_args()
 
 
@@ -92,8 +98,9 @@ def cpu_baseline(problem, M, budget):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the path shards by "
-                                   "sample range across GPUs, see DESIGN.md)"}))
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the path would shard "
+                                   "by sample range across GPUs, with one all-reduce of the level moments "
+                                   "per Algorithm-1 round)"}))
         sys.exit(2)
     import torch
 
@@ -109,9 +116,11 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_per_launch": 2 * src.numel() * 4, "launches": 4}), flush=True)
         return
-    base = W.config2(N=1e4)
-
     os.environ.setdefault("DK_LOG", "1")     # progress lines on stderr (per round and per long launch)
+    if args.workload != "config2":
+        {"config3": bench_config3, "config4": bench_config4, "config5": bench_config5}[args.workload](args)
+        return
+    base = W.config2(N=1e4)
 
     def one(seed, ctx, eps):
         p = base.with_(seed=seed)
@@ -197,6 +206,149 @@ def main():
         out["cpu_baseline"] = cpu_baseline(base, last["M"], args.cpu_budget)
     print(json.dumps(out), flush=True)
 
+
+
+def _report(workload, value, unit, extra):
+    line = {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "data": "synthetic",
+            "config": {"workload": workload}, "report_only": True}
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+
+
+def bench_config3(args):
+    """Low-density MLMC (config 3): rho0 = max(0, cos 2 pi x) + 0.05, levels 8^2..256^2, 29
+    observables (Fourier modes |k| <= 3 and the primary, a squared bump), N = 1e5 and 1e3.
+    1. Variance profile: one round of 1000 samples on every level (the resident levels in one
+       persistent launch, the 256^2 pairs on the streaming kernel): Y_l and V_l per level show
+       the low-density behaviour (V_l stops decreasing once N h^2 rho is small).
+    2. Algorithm 1 with persistent rounds.  The primary observable is uncentred and unscaled
+       (about 1.5e-4), so the accuracy is relative to its magnitude, estimated by a 1000-sample
+       level-0 pilot from another noise stream: 1e-3 at N = 1e5 (reaches 256^2) and 3e-2 at
+       N = 1e3 (where the growing V_l make tighter targets cost hours); --N with --eps overrides.
+    Reports wall times, the share of wall time outside kernels, the tuner's choices and the
+    per-level statistics."""
+    import torch
+    import dk_workloads as W
+    import paper_2311_08872_amd as dk
+    runs = [(args.N, args.eps)] if args.N else [(1e5, 1e-3), (1e3, 3e-2)]
+    for N, rel in runs:
+        p = W.config3(N=N)
+        L = p.levels - 1
+        ctx = dk.Context(0)
+        dk.round_sums(p, L, [0] * (L + 1), [64] * (L + 1), tag=W.TAG_MC, round_mode=3, ctx=ctx)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prof = dk.round_sums(p, L, [0] * (L + 1), [1000] * (L + 1), round_mode=3, ctx=ctx)
+        torch.cuda.synchronize()
+        t_prof = time.perf_counter() - t0
+        Y, V = [], []
+        for l in range(L + 1):
+            m = prof[l][p.primary]
+            Y.append(m.sums[0] / m.count)
+            V.append(max(0.0, (m.sums[1] - m.sums[0] ** 2 / m.count) / (m.count - 1)))
+        pilot = dk.round_sums(p, 0, [0], [1000], tag=W.TAG_MC, round_mode=3, ctx=ctx)[0][p.primary]
+        scale = abs(pilot.sums[2] / pilot.count)
+        eps = rel * scale
+        ctx.close()
+        ctx = dk.Context(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = dk.estimate(p, eps, ctx=ctx, round_mode=3)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = ctx.stats()
+        kernel_ms = sum(s["kernel_ms"] for s in st)
+        tuned = json.loads(ctx.tuning_json())
+        ctx.close()
+        _report(f"config-3 low-density MLMC: rho0=max(0,cos2pix)+0.05, h=1/8..1/256, N={N:g}, 29 observables, "
+                f"eps={rel:g} relative ({eps:.3g} absolute), persistent rounds", wall, "s",
+                {"eps_abs": eps, "kernel_fraction_of_wall": kernel_ms / 1e3 / wall,
+                 "variance_profile": {"samples_per_level": 1000, "wall_s": t_prof, "Y": Y, "V": V,
+                                      "N_h2_min_density": [N * 0.05 / p.n(l) ** 2 for l in range(L + 1)]},
+                 "mlmc": {k: r[k] for k in ("L", "converged", "M", "Yhat", "Vhat", "rmse_est", "rounds",
+                                            "cell_updates", "estimate")},
+                 "cell_updates_per_s": r["cell_updates"] / wall, "tuned_shapes": tuned["shapes"],
+                 "kernels": [{k: s[k] for k in ("level", "coupled", "launches", "samples", "kernel_ms",
+                                                "cell_updates", "rows")} for s in st]})
+
+
+def bench_config4(args):
+    """Learned control variate (config 4): for every pair l >= 1 of config 2, a network trained on
+    2^16 pairs from its own noise stream, then Algorithm 1 to args.eps with the control variate on
+    levels 1..4 (4 independent coarse-only paths per pair).  Wall time includes the training.
+    Reports each network's held-out variance ratio Var(Y - r) / Var(Y)."""
+    import numpy as np
+    import torch
+    import dk_workloads as W
+    import paper_2311_08872_amd as dk
+    p = W.config2(N=1e4)
+    ctx = dk.Context(0)
+    dk.estimate(p.with_(seed=1000), 2e-2, ctx=ctx)                      # warm-up (untimed)
+    ctx.close()
+    ctx = dk.Context(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    params = np.zeros((p.levels, dk.L.DK_CNN_NPARAM), np.float32)
+    train = {}
+    for l in range(1, p.levels):
+        t1 = time.perf_counter()
+        res = dk.cv_train(p, l, n_train=1 << 16, epochs=6, batch=256, lr=1e-3, n_val=1 << 13, seed=l, ctx=ctx)
+        params[l] = res["params"]
+        train[l] = {"s": time.perf_counter() - t1, "var_Y": res["var_Y"], "var_Y_minus_r": res["var_Y_minus_r"],
+                    "var_r": res["var_r"], "ratio": res["var_Y_minus_r"] / res["var_Y"]}
+        print(f"[bench] config4 level {l} trained: ratio {train[l]['ratio']:.4f}", file=sys.stderr, flush=True)
+    t_train = time.perf_counter() - t0
+    r = dk.estimate(p, args.eps, ctx=ctx, cv_params=params, cv_level_mask=0b11110, cv_ratio=4)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.close()
+    _report(f"config-4 learned control variate on config-2 pairs l=1..4 (2^16 training pairs per level), "
+            f"eps={args.eps:g}", wall, "s",
+            {"train_s": t_train, "train": train,
+             "mlmc": {k: r[k] for k in ("L", "converged", "M", "Yhat", "Vhat", "rmse_est", "rounds", "cell_updates")}})
+
+
+def bench_config5(args):
+    """Throughput scale (config 5): finest grids 256^2, 512^2 and 1024^2 (levels 4..6 of h = 1/16 ..
+    1/1024, N = 1e6, T = 26 tau_0), coupled pairs on the streaming kernel (state in HBM, 4 fine
+    steps per launch); args.samples pairs at 1024^2 and correspondingly more at the smaller grids.
+    Also the noise-free FP32 stencil, which is bound by HBM bandwidth."""
+    import torch
+    import dk_workloads as W
+    import paper_2311_08872_amd as dk
+    N = args.N or 1e6
+    p = W.config5(N=N)
+    out = {}
+    ctx = dk.Context(0)
+    dk.level_pair(p, 4, 0, 64, ctx=ctx)                                 # warm-up (untimed)
+    for l in (4, 5, 6):
+        cnt = args.samples * 4 ** (6 - l)
+        ctx.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dk.level_pair(p, l, 0, cnt, ctx=ctx)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = [s for s in ctx.stats() if s["level"] == l][0]
+        cells = st["cell_updates"]
+        out[f"{p.n(l)}"] = {"pairs": cnt, "wall_s": wall, "kernel_ms": st["kernel_ms"],
+                            "cell_updates_per_s": cells / (st["kernel_ms"] / 1e3),
+                            "algorithmic_GB_per_s": 5.0 * cells / (st["kernel_ms"] / 1e3) / 1e9}
+        print(f"[bench] config5 {p.n(l)}^2: {out[str(p.n(l))]['cell_updates_per_s']:.3g} cell updates/s",
+              file=sys.stderr, flush=True)
+    heat = {}
+    for n, batch in ((256, 4096), (1024, 256)):
+        x = torch.ones((batch, n, n), dtype=torch.float32, device="cuda")
+        dk.heat_steps(x, 4, p.mu, ctx=ctx)
+        dt = dk.heat_steps(x, 64, p.mu, ctx=ctx) / 1e3      # kernel time of the 64 steps
+        heat[f"{n}"] = {"batch": batch, "GB_per_s": 8.0 * batch * n * n * 64 / dt / 1e9,
+                        "frac_of_8TBps": 8.0 * batch * n * n * 64 / dt / 8e12}
+        del x
+    ctx.close()
+    fin = out[f"{p.n(6)}"]
+    _report(f"config-5 throughput: coupled pairs at 256^2, 512^2, 1024^2 (N={N:g}, tau=0.1h^2, "
+            f"{args.samples} pairs at 1024^2), streaming kernel", fin["cell_updates_per_s"], "cell updates/s",
+            {"grids": out, "noise_free_stencil": heat})
 
 if __name__ == "__main__":
     main()
