@@ -161,6 +161,12 @@ typedef struct {
                                  sums moments per task, so its results agree with mode 0's to
                                  rounding (per-sample paths are the same).                         */
     int32_t reserved;
+    const char* checkpoint_path; /* NULL, or a file for Algorithm-1 checkpoints: after every round
+                                 the state (levels, samples done and targeted, compensated sums) is
+                                 written to path.tmp and renamed over path.  A run that finds the
+                                 file resumes after its last round and gives bit-identical results
+                                 to an uninterrupted run; a file of another run (problem, eps or
+                                 options differ) gives DK_EINVAL.  MLMC only (not plain MC).      */
 } dk_mlmc_opts;
 
 typedef struct {

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <string>
@@ -1077,11 +1078,124 @@ double bias_remainder(const std::vector<double>& Y, int L, double alpha)
     return r / (std::pow(2.0, alpha) - 1.0);
 }
 
+// ------------------------------------------------------------------------------------------
+// Algorithm-1 checkpoints: after every completed round the state (level, round count, samples
+// done and targeted, compensated sums, and whatever the sampler adds) is written as text, doubles
+// as their bit patterns, to path.tmp and renamed over path.  A run that finds the file resumes
+// from it; since the sample ranges of every round follow from that state and the noise is a pure
+// function of the sample index, the resumed run reproduces the uninterrupted one bit for bit.
+// ------------------------------------------------------------------------------------------
+struct CkptHooks {
+    uint64_t key = 0;                                         // identifies the run
+    std::function<void(std::vector<double>&)> save;           // extra sampler state
+    std::function<int(const std::vector<double>&)> load;
+};
+
+struct Fnv {
+    uint64_t h = 1469598103934665603ull;
+    void bytes(const void* p, size_t n)
+    {
+        const unsigned char* c = (const unsigned char*)p;
+        for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
+    }
+    template <class T> void val(const T& v) { bytes(&v, sizeof(v)); }
+};
+
+uint64_t alg1_key(double eps, int L_max, const double* cost, const dk_mlmc_opts& o)
+{
+    Fnv f;
+    f.val(eps); f.val(L_max);
+    for (int l = 0; l <= L_max; ++l) f.val(cost[l]);
+    f.val(o.m_pilot); f.val(o.L_start); f.val(o.alpha); f.val(o.max_samples);
+    return f.h;
+}
+
+std::string hex_bits(double v)
+{
+    uint64_t b;
+    std::memcpy(&b, &v, 8);
+    char buf[24];
+    std::snprintf(buf, sizeof(buf), "%016llx", (unsigned long long)b);
+    return buf;
+}
+
+double from_bits(const std::string& t)
+{
+    const uint64_t b = std::strtoull(t.c_str(), nullptr, 16);
+    double v;
+    std::memcpy(&v, &b, 8);
+    return v;
+}
+
+struct Alg1State {
+    int L = 0, rounds = 0;
+    std::vector<uint64_t> done, target;
+    std::vector<double> s1, c1, s2, c2, extra;
+};
+
+int write_checkpoint(const char* path, uint64_t key, const Alg1State& S)
+{
+    const std::string tmp = std::string(path) + ".tmp";
+    {
+        std::ofstream f(tmp);
+        if (!f) return fail(DK_EINVAL, "cannot write checkpoint %s", tmp.c_str());
+        char k[24];
+        std::snprintf(k, sizeof(k), "%016llx", (unsigned long long)key);
+        f << "dk-alg1-checkpoint 1\nkey " << k << "\nL " << S.L << " rounds " << S.rounds << " levels "
+          << S.done.size() << "\n";
+        for (size_t l = 0; l < S.done.size(); ++l)
+            f << S.done[l] << " " << S.target[l] << " " << hex_bits(S.s1[l]) << " " << hex_bits(S.c1[l]) << " "
+              << hex_bits(S.s2[l]) << " " << hex_bits(S.c2[l]) << "\n";
+        f << "extra " << S.extra.size();
+        for (double v : S.extra) f << " " << hex_bits(v);
+        f << "\nend\n";
+        if (!f) return fail(DK_EINVAL, "cannot write checkpoint %s", tmp.c_str());
+    }
+    if (std::rename(tmp.c_str(), path) != 0) return fail(DK_EINVAL, "cannot rename checkpoint to %s", path);
+    return DK_OK;
+}
+
+// 1: state loaded; 0: no file; < 0: error (unreadable, another run's file, wrong shape)
+int read_checkpoint(const char* path, uint64_t key, int levels, Alg1State& S)
+{
+    std::ifstream f(path);
+    if (!f) return 0;
+    std::string w, k;
+    int version = 0;
+    size_t nl = 0;
+    if (!(f >> w >> version) || w != "dk-alg1-checkpoint" || version != 1)
+        return fail(DK_EINVAL, "%s is not an Algorithm-1 checkpoint", path);
+    char want[24];
+    std::snprintf(want, sizeof(want), "%016llx", (unsigned long long)key);
+    if (!(f >> w >> k) || w != "key") return fail(DK_EINVAL, "checkpoint %s: no key", path);
+    if (k != want) return fail(DK_EINVAL, "checkpoint %s belongs to another run (problem, eps or options differ)", path);
+    std::string wl, wr, wv;
+    if (!(f >> wl >> S.L >> wr >> S.rounds >> wv >> nl) || wl != "L" || wr != "rounds" || wv != "levels" ||
+        (int)nl != levels || S.L < 0 || S.L >= levels || S.rounds < 0)
+        return fail(DK_EINVAL, "checkpoint %s: bad header", path);
+    S.done.assign(nl, 0); S.target.assign(nl, 0);
+    S.s1.assign(nl, 0); S.c1.assign(nl, 0); S.s2.assign(nl, 0); S.c2.assign(nl, 0);
+    for (size_t l = 0; l < nl; ++l) {
+        std::string a, b, c, d;
+        if (!(f >> S.done[l] >> S.target[l] >> a >> b >> c >> d)) return fail(DK_EINVAL, "checkpoint %s: bad level line", path);
+        S.s1[l] = from_bits(a); S.c1[l] = from_bits(b); S.s2[l] = from_bits(c); S.c2[l] = from_bits(d);
+    }
+    size_t ne = 0;
+    if (!(f >> w >> ne) || w != "extra" || ne > (1u << 24)) return fail(DK_EINVAL, "checkpoint %s: bad extra", path);
+    S.extra.resize(ne);
+    for (size_t i = 0; i < ne; ++i) {
+        if (!(f >> w)) return fail(DK_EINVAL, "checkpoint %s: truncated", path);
+        S.extra[i] = from_bits(w);
+    }
+    if (!(f >> w) || w != "end") return fail(DK_EINVAL, "checkpoint %s: truncated", path);
+    return 1;
+}
+
 // optional: all levels of one round at once; sums [L+1][2]
 typedef int (*round_sampler)(void* user, int L, const uint64_t* first, const uint64_t* count, double* sums);
 
 int alg1_core(double eps, int L_max, const double* cost, const dk_mlmc_opts& o, dk_level_sampler sampler, void* user,
-              dk_mlmc_result* out, round_sampler rsampler = nullptr)
+              dk_mlmc_result* out, round_sampler rsampler = nullptr, const CkptHooks* ck = nullptr)
 {
     if (!(eps > 0)) return fail(DK_EINVAL, "eps must be > 0");
     if (L_max < 0 || L_max >= DK_MAX_LEVELS) return fail(DK_EINVAL, "L_max out of range");
@@ -1103,6 +1217,25 @@ int alg1_core(double eps, int L_max, const double* cost, const dk_mlmc_opts& o, 
     };
     int rounds = 0;
     bool conv = false;
+    const char* ckpath = o.checkpoint_path && *o.checkpoint_path ? o.checkpoint_path : nullptr;
+    const uint64_t ckkey = alg1_key(eps, L_max, cost, o) ^ (ck ? ck->key * 0x9E3779B97F4A7C15ull : 0);
+    if (ckpath) {
+        Alg1State S;
+        const int rc = read_checkpoint(ckpath, ckkey, L_max + 1, S);
+        if (rc < 0) return rc;
+        if (rc == 1) {
+            L = S.L; rounds = S.rounds; done = S.done; target = S.target;
+            s1 = S.s1; c1 = S.c1; s2 = S.s2; c2 = S.c2;
+            if (ck && ck->load) {
+                const int lr = ck->load(S.extra);
+                if (lr < 0) return lr;
+            }
+            if (std::getenv("DK_LOG")) {
+                std::fprintf(stderr, "[dk] resumed from %s after round %d (L=%d)\n", ckpath, rounds, L);
+                std::fflush(stderr);
+            }
+        }
+    }
     for (;;) {
         bool need = false;
         for (int l = 0; l <= L; ++l) need |= target[l] > done[l];
@@ -1162,6 +1295,14 @@ int alg1_core(double eps, int L_max, const double* cost, const dk_mlmc_opts& o, 
             uint64_t mi = m > 1.8e19 ? (uint64_t)1.8e19 : (uint64_t)m;
             if (o.max_samples && mi > o.max_samples) mi = o.max_samples;
             target[l] = std::max(done[l], mi);
+        }
+        if (ckpath) {
+            Alg1State S;
+            S.L = L; S.rounds = rounds; S.done = done; S.target = target;
+            S.s1 = s1; S.c1 = c1; S.s2 = s2; S.c2 = c2;
+            if (ck && ck->save) ck->save(S.extra);
+            const int rc = write_checkpoint(ckpath, ckkey, S);
+            if (rc < 0) return rc;
         }
     }
     stats(L);
@@ -1895,6 +2036,8 @@ int dk_mlmc_estimate(dk_context* ctx, const dk_problem* problem, double eps, con
                 if (nc % 4) return fail(DK_EINVAL, "control variate on level %d: coarse grid must be a multiple of 4", l);
             }
     }
+    if (mc && o.checkpoint_path && *o.checkpoint_path)
+        return fail(DK_EINVAL, "checkpoint_path applies to MLMC runs, not plain MC");
     if (!mc) {
         std::vector<double> cost(problem->levels);
         for (int l = 0; l < problem->levels; ++l) {
@@ -1903,8 +2046,42 @@ int dk_mlmc_estimate(dk_context* ctx, const dk_problem* problem, double eps, con
         }
         G.round_mode = o.round_mode;
         if (o.round_mode < 0 || o.round_mode > 3) return fail(DK_EINVAL, "round_mode must be 0, 1, 2 or 3");
+        // checkpoints: the key covers everything that changes the samples or their grouping; the
+        // sampler's per-observable moments and cell count travel with the state
+        CkptHooks ck;
+        {
+            Fnv f;
+            f.val(problem_hash(problem));
+            f.val(G.cv_mask); f.val(G.cv_ratio); f.val(o.round_mode == 3);
+            if (G.cv_params) f.bytes(G.cv_params, sizeof(float) * (size_t)problem->levels * dk::cnn::NPARAM);
+            ck.key = f.h;
+        }
+        auto put = [](std::vector<double>& v, const dk_moments& m) {
+            v.push_back((double)m.count);
+            for (int k = 0; k < DK_NMOM; ++k) { v.push_back(m.sum[k]); v.push_back(m.comp[k]); }
+        };
+        ck.save = [&](std::vector<double>& v) {
+            v.clear();
+            v.push_back(G.cell_updates);
+            for (const dk_moments& m : G.mom) put(v, m);
+            for (const dk_moments& m : G.zmom) put(v, m);
+        };
+        ck.load = [&](const std::vector<double>& v) -> int {
+            const size_t per = 1 + 2 * DK_NMOM;
+            if (v.size() != 1 + per * (G.mom.size() + G.zmom.size()))
+                return fail(DK_EINVAL, "checkpoint: sampler state of another shape");
+            size_t i = 0;
+            G.cell_updates = v[i++];
+            auto get = [&](dk_moments& m) {
+                m.count = (uint64_t)v[i++];
+                for (int k = 0; k < DK_NMOM; ++k) { m.sum[k] = v[i++]; m.comp[k] = v[i++]; }
+            };
+            for (dk_moments& m : G.mom) get(m);
+            for (dk_moments& m : G.zmom) get(m);
+            return DK_OK;
+        };
         rc = alg1_core(eps, problem->levels - 1, cost.data(), o, gpu_sample, &G, out,
-                       o.round_mode > 0 ? gpu_round : nullptr);
+                       o.round_mode > 0 ? gpu_round : nullptr, &ck);
         if (rc < 0) return rc;
     } else {
         // plain MC on one level: pilot, then M = ceil(2 V / eps^2) so that V / M <= eps^2 / 2

@@ -92,3 +92,41 @@ def test_host_algorithm1_not_converged_and_errors(dk):
         raise ValueError("sampler failure")
     with pytest.raises(ValueError):
         dk.alg1_host(1e-2, 3, [1, 16, 256, 4096], failing)
+
+
+def test_host_algorithm1_checkpoint_resume_is_bit_identical(dk, tmp_path):
+    """A run killed inside a round resumes from its checkpoint and ends exactly where the
+    uninterrupted run ends; the finished run's checkpoint reproduces the result without sampling;
+    another run's file and a damaged file are rejected."""
+    L_max = 5
+    means = [1.0] + [0.5 * 4.0 ** -l for l in range(1, L_max + 1)]
+    sds = [1.0] + [0.5 * 2.0 ** -l for l in range(1, L_max + 1)]
+    cost = [16.0 ** l for l in range(L_max + 1)]
+    s = exact_sampler(means, sds)
+    full = dk.alg1_host(2e-3, L_max, cost, s, m_pilot=500)
+    assert full["rounds"] >= 3
+    path = tmp_path / "alg1.ckpt"
+    calls = {"n": 0}
+
+    def killed(level, first, count):
+        calls["n"] += 1
+        if calls["n"] == 7:
+            raise RuntimeError("killed")
+        return s(level, first, count)
+    with pytest.raises(RuntimeError):
+        dk.alg1_host(2e-3, L_max, cost, killed, m_pilot=500, checkpoint_path=path)
+    assert path.exists()
+    resumed = dk.alg1_host(2e-3, L_max, cost, s, m_pilot=500, checkpoint_path=path)
+    for k in ("L", "converged", "rounds", "M", "Yhat", "Vhat", "estimate", "var_est", "rmse_est"):
+        assert resumed[k] == full[k], k
+
+    def never(level, first, count):
+        raise AssertionError("a finished run must not sample again")
+    again = dk.alg1_host(2e-3, L_max, cost, never, m_pilot=500, checkpoint_path=path)
+    assert again["M"] == full["M"] and again["estimate"] == full["estimate"]
+    with pytest.raises(dk.DKError):
+        dk.alg1_host(1e-3, L_max, cost, s, m_pilot=500, checkpoint_path=path)     # another eps
+    text = path.read_text()
+    path.write_text(text[: len(text) // 2])
+    with pytest.raises(dk.DKError):
+        dk.alg1_host(2e-3, L_max, cost, s, m_pilot=500, checkpoint_path=path)

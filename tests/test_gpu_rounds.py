@@ -127,3 +127,26 @@ def test_persistent_estimate_agrees_with_level_path():
         import math
         for x, y, v in zip(a["estimate"], b["estimate"], b["var_est"]):
             assert abs(x - y) <= 4.5 * math.sqrt(2 * v) + 1e-12
+
+
+@pytest.mark.parametrize("mode", [0, 3])
+def test_checkpoint_resume_is_bit_identical(tmp_path, mode):
+    """dk_mlmc_estimate stopped after two rounds (max_rounds) resumes from its checkpoint file and
+    returns exactly the uninterrupted run's result, per-observable moments and cell count included."""
+    p = W.config2(N=1e4).with_(seed=4)
+    print(f"[gpu] checkpoint mode={mode}: uninterrupted", flush=True)
+    ctx = dk.Context(0)
+    full = dk.estimate(p, 1e-2, ctx=ctx, round_mode=mode, level_moments=True)
+    assert full["rounds"] > 2
+    path = tmp_path / "est.ckpt"
+    print(f"[gpu] checkpoint mode={mode}: stopped after 2 rounds", flush=True)
+    with pytest.raises(dk.DKError):
+        dk.estimate(p, 1e-2, ctx=ctx, round_mode=mode, max_rounds=2, checkpoint_path=path)
+    print(f"[gpu] checkpoint mode={mode}: resumed", flush=True)
+    res = dk.estimate(p, 1e-2, ctx=ctx, round_mode=mode, checkpoint_path=path, level_moments=True)
+    ctx.close()
+    for k in ("L", "converged", "rounds", "M", "Yhat", "Vhat", "estimate", "var_est", "cell_updates"):
+        assert res[k] == full[k], k
+    for a, b in zip(res["level_moments"], full["level_moments"]):
+        for ma, mb in zip(a, b):
+            assert ma.count == mb.count and (ma.sums == mb.sums).all()
