@@ -9,11 +9,13 @@
 // sequence (no contraction inside; every fused multiply-add is written explicitly):
 //   radius word a -> odd integer w = 2 (a >> 9) + 1, u = w 2^-24;
 //     w = 2^e m, m in [1, 2), folded into [sqrt(1/2), sqrt(2)];
-//     ln u = (e - 24) ln 2 + 2 atanh((m - 1)/(m + 1)), atanh by its odd power series to s^11;
+//     ln u = (e - 24) ln 2 + x g(x), x = m - 1 (exact), g(x) = ln(1 + x)/x by the degree-10
+//     polynomial interpolating g at the 11 Chebyshev nodes of [sqrt(1/2) - 1, sqrt(2) - 1]
+//     (coefficients rounded to binary32; error below the rounding of the result; no division);
 //     R = sqrt(-2 ln u)   (|R| <= sqrt(48 ln 2), a tail cut at probability ~1e-8)
 //   angle word b -> quadrant b >> 30 and fraction f = (2 ((b >> 7) & 0x7fffff) + 1) 2^-24;
 //     the angle inside the quadrant is reduced to at most pi/4 by the complement, and its
-//     sine and cosine come from their Taylor series to degree 11 and 12;
+//     sine and cosine come from their Taylor series to degree 9 and 10 (next terms < 2e-9);
 //   (z0, z1) = R (cos, sin)(pi/2 (q + f)).
 #pragma once
 #include <hip/hip_runtime.h>
@@ -51,18 +53,22 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, fl
     int e = 31 - __builtin_clz(w);
     float m = (float)w * pow2_neg(e);
     if (m > 1.41421356f) { m = m * 0.5f; e += 1; }
-    const float s = (m - 1.0f) / (m + 1.0f);   // correctly rounded (built with -fhip-fp32-correctly-rounded-divide-sqrt)
-    const float t = s * s;
-    float p = __builtin_fmaf(1.0f / 11.0f, t, 1.0f / 9.0f);
-    p = __builtin_fmaf(p, t, 1.0f / 7.0f);
-    p = __builtin_fmaf(p, t, 1.0f / 5.0f);
-    p = __builtin_fmaf(p, t, 1.0f / 3.0f);
-    p = p * t;
-    const float ath = __builtin_fmaf(s, p, s);
+    const float xm = m - 1.0f;   // exact
+    float gx = __builtin_fmaf(0x1.0d33dap-4f, xm, -0x1.dbfb56p-4f);
+    gx = __builtin_fmaf(gx, xm, 0x1.e94d9cp-4f);
+    gx = __builtin_fmaf(gx, xm, -0x1.fcc1c0p-4f);
+    gx = __builtin_fmaf(gx, xm, 0x1.231156p-3f);
+    gx = __builtin_fmaf(gx, xm, -0x1.5554c0p-3f);
+    gx = __builtin_fmaf(gx, xm, 0x1.99a6e4p-3f);
+    gx = __builtin_fmaf(gx, xm, -0x1.00002ap-2f);
+    gx = __builtin_fmaf(gx, xm, 0x1.555540p-2f);
+    gx = __builtin_fmaf(gx, xm, -0.5f);
+    gx = __builtin_fmaf(gx, xm, 1.0f);
+    const float lnm = xm * gx;
     const float ne = (float)(e - 24);
     const float hi = ne * 0x1.62ep-1f;
-    const float lo = __builtin_fmaf(ne, (float)(0.69314718055994530942 - 0.693115234375), 2.0f * ath);
-    const float R = __builtin_sqrtf(-2.0f * (hi + lo));   // correctly rounded, as the division
+    const float lo = __builtin_fmaf(ne, (float)(0.69314718055994530942 - 0.693115234375), lnm);
+    const float R = __builtin_sqrtf(-2.0f * (hi + lo));   // correctly rounded (built with -fhip-fp32-correctly-rounded-divide-sqrt)
 
     const uint32_t q = b >> 30;
     const float f = (float)((((b >> 7) & 0x7FFFFFu) << 1) | 1u) * 0x1p-24f;
@@ -70,13 +76,11 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, fl
     const float g = flip ? 1.0f - f : f;
     const float x = g * 0x1.921fb6p+0f;
     const float x2 = x * x;
-    float ps = __builtin_fmaf(-1.0f / 39916800.0f, x2, 1.0f / 362880.0f);
-    ps = __builtin_fmaf(ps, x2, -1.0f / 5040.0f);
+    float ps = __builtin_fmaf(1.0f / 362880.0f, x2, -1.0f / 5040.0f);
     ps = __builtin_fmaf(ps, x2, 1.0f / 120.0f);
     ps = __builtin_fmaf(ps, x2, -1.0f / 6.0f);
     const float sn = __builtin_fmaf(x * x2, ps, x);
-    float pc = __builtin_fmaf(1.0f / 479001600.0f, x2, -1.0f / 3628800.0f);
-    pc = __builtin_fmaf(pc, x2, 1.0f / 40320.0f);
+    float pc = __builtin_fmaf(-1.0f / 3628800.0f, x2, 1.0f / 40320.0f);
     pc = __builtin_fmaf(pc, x2, -1.0f / 720.0f);
     pc = __builtin_fmaf(pc, x2, 1.0f / 24.0f);
     pc = __builtin_fmaf(pc, x2, -0.5f);
