@@ -53,7 +53,7 @@ __device__ __forceinline__ double lane_get(int addr, double v)
 template <typename Real>
 __device__ __forceinline__ Real pos_sqrt(Real x) { return x > Real(0) ? sqrt(x) : Real(0); }
 template <>
-__device__ __forceinline__ float pos_sqrt<float>(float x) { return x > 0.0f ? __builtin_amdgcn_sqrtf(x) : 0.0f; }
+__device__ __forceinline__ float pos_sqrt<float>(float x) { return __builtin_amdgcn_sqrtf(__builtin_fmaxf(x, 0.0f)); }
 
 // ---------------------------------------------------------------------------------------
 // Noise sources for one tile step: row(i, w0, w1) yields the unit noise of the tile's row i

@@ -31,10 +31,10 @@ __device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1)
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
-        U4 n;
-        n.x = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
+        U4 n;   // the three-way XORs are single gfx950 bitop3 instructions (truth table 0x96)
+        n.x = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c.y, k0, 0x96);
         n.y = (uint32_t)p1;
-        n.z = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+        n.z = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c.w, k1, 0x96);
         n.w = (uint32_t)p0;
         c = n;
         k0 += 0x9E3779B9u;
@@ -43,16 +43,20 @@ __device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1)
     return c;
 }
 
-// 2^-e as a binary32 bit pattern (0 <= e <= 24)
-__device__ __forceinline__ float pow2_neg(int e) { return __int_as_float((127 - e) << 23); }
-
+// The sequence below is that definition written with integer bit operations where the
+// definition selects or negates (the same values, bit for bit, without lane-mask hazards):
+//   the fold:  m > binary32(1.41421356) iff the significand field of (float)w exceeds 0x3504f3;
+//   the complement angle:  1 - f = (2 (j ^ 0x7fffff) + 1) 2^-24 exactly, and f > 1/2 iff bit 22 of j;
+//   the quadrant turn:  (c, s) -> (-s, c) twice folds into one swap and two sign-bit flips.
 __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, float& z1)
 {
 #pragma clang fp contract(off)
-    const uint32_t w = ((a >> 9) << 1) | 1u;
-    int e = 31 - __builtin_clz(w);
-    float m = (float)w * pow2_neg(e);
-    if (m > 1.41421356f) { m = m * 0.5f; e += 1; }
+    const uint32_t w = ((a >> 9) << 1) | 1u;                 // odd, < 2^24, so (float)w is exact
+    const uint32_t wb = __float_as_uint((float)w);
+    const uint32_t mant = wb & 0x7FFFFFu;
+    const uint32_t fold = (0x3504F3u - mant) >> 31;          // 1 iff w 2^-e > binary32(1.41421356)
+    const float m = __uint_as_float(mant | ((127u - fold) << 23));   // in [sqrt(1/2), sqrt(2)]
+    const float ne = (float)((int)(wb >> 23) + (int)fold - 151);     // e - 24
     const float xm = m - 1.0f;   // exact
     float gx = __builtin_fmaf(0x1.0d33dap-4f, xm, -0x1.dbfb56p-4f);
     gx = __builtin_fmaf(gx, xm, 0x1.e94d9cp-4f);
@@ -65,15 +69,14 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, fl
     gx = __builtin_fmaf(gx, xm, -0.5f);
     gx = __builtin_fmaf(gx, xm, 1.0f);
     const float lnm = xm * gx;
-    const float ne = (float)(e - 24);
     const float hi = ne * 0x1.62ep-1f;
     const float lo = __builtin_fmaf(ne, (float)(0.69314718055994530942 - 0.693115234375), lnm);
     const float R = __builtin_sqrtf(-2.0f * (hi + lo));   // correctly rounded (built with -fhip-fp32-correctly-rounded-divide-sqrt)
 
     const uint32_t q = b >> 30;
-    const float f = (float)((((b >> 7) & 0x7FFFFFu) << 1) | 1u) * 0x1p-24f;
-    const bool flip = f > 0.5f;
-    const float g = flip ? 1.0f - f : f;
+    const uint32_t flip = (b >> 29) & 1u;                    // f > 1/2
+    const uint32_t j = ((b >> 7) & 0x7FFFFFu) ^ ((0u - flip) & 0x7FFFFFu);
+    const float g = (float)((j << 1) | 1u) * 0x1p-24f;       // f, or 1 - f when f > 1/2
     const float x = g * 0x1.921fb6p+0f;
     const float x2 = x * x;
     float ps = __builtin_fmaf(1.0f / 362880.0f, x2, -1.0f / 5040.0f);
@@ -85,15 +88,15 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, fl
     pc = __builtin_fmaf(pc, x2, 1.0f / 24.0f);
     pc = __builtin_fmaf(pc, x2, -0.5f);
     const float cs = __builtin_fmaf(x2, pc, 1.0f);
-    const float cq = flip ? sn : cs;
-    const float sq = flip ? cs : sn;
-    // rotate by q quarter turns: (c, s) -> (-s, c)
-    const float c1 = (q & 1u) ? -sq : cq;
-    const float s1 = (q & 1u) ? cq : sq;
-    const float c2 = (q & 2u) ? -c1 : c1;
-    const float s2 = (q & 2u) ? -s1 : s1;
-    z0 = R * c2;
-    z1 = R * s2;
+    // cos and sin of the quadrant's angle; each odd quarter turn swaps them, and the signs of
+    // cos and sin flip in quadrants (1, 2) and (2, 3)
+    const bool swap = (flip ^ (q & 1u)) != 0u;
+    const float c = swap ? sn : cs;
+    const float s = swap ? cs : sn;
+    const uint32_t csign = ((q ^ (q >> 1)) & 1u) << 31;
+    const uint32_t ssign = (q >> 1) << 31;
+    z0 = R * __uint_as_float(__float_as_uint(c) ^ csign);
+    z1 = R * __uint_as_float(__float_as_uint(s) ^ ssign);
 }
 
 // Normals of the horizontal site pair (2a, y), (2a+1, y) at fine step m.

@@ -37,7 +37,7 @@ constexpr int CT = TT / 2;           // coarse tile interior (32)
 constexpr int CEXT = CT + 2;         // coarse tile with a 1-cell halo (34)
 
 __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
-__device__ __forceinline__ float psq(float x) { return x > 0.0f ? __builtin_amdgcn_sqrtf(x) : 0.0f; }
+__device__ __forceinline__ float psq(float x) { return __builtin_amdgcn_sqrtf(__builtin_fmaxf(x, 0.0f)); }
 }  // namespace
 
 template <int FLUX, bool PAIR>
