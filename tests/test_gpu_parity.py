@@ -68,7 +68,9 @@ def test_config2_per_sample_parity(level, count):
     torch.cuda.synchronize()
     gpu = ps.cpu().numpy()
     ref = oracle.run_range(oracle.OracleProblem(p), level, 0, count)
-    assert scaled_err(gpu, ref) <= TOL
+    err = scaled_err(gpu, ref)
+    banner(f"scaled FP32-vs-FP64 error {err:.3g} (tolerance {TOL:g})")
+    assert err <= TOL
 
 
 def test_config2_finest_pair_sampled():
@@ -90,6 +92,7 @@ def test_config2_finest_pair_sampled():
     # scale by the batch RMS of the GPU values (the oracle is only run on 4 samples)
     rms = np.sqrt(np.mean(gpu ** 2, axis=0, keepdims=True))
     err = np.max(np.abs(allg - ref) / np.maximum(np.abs(ref), rms))
+    banner(f"scaled FP32-vs-FP64 error {err:.3g} (tolerance {TOL:g})")
     assert err <= TOL, err
 
 
@@ -106,7 +109,9 @@ def test_fields_and_flux_modes(flux, level):
         assert np.max(np.abs(rf[i].double().cpu().numpy() - f)) <= TOL * np.max(np.abs(f))
         assert np.max(np.abs(rc[i].double().cpu().numpy() - c)) <= TOL * np.max(np.abs(c))
     ref = oracle.run_range(op, level, 40, 24)
-    assert scaled_err(ps.cpu().numpy(), ref) <= TOL
+    err = scaled_err(ps.cpu().numpy(), ref)
+    banner(f"scaled FP32-vs-FP64 error {err:.3g} (tolerance {TOL:g})")
+    assert err <= TOL
 
 
 def test_config1_fp64_state():
@@ -127,7 +132,9 @@ def test_config1_fp32_and_moments():
     torch.cuda.synchronize()
     gpu = ps.cpu().numpy()
     ref = oracle.run_range(oracle.OracleProblem(p), 0, 0, 1000, tag=W.TAG_MC)
-    assert scaled_err(gpu, ref) <= TOL
+    err = scaled_err(gpu, ref)
+    banner(f"scaled FP32-vs-FP64 error {err:.3g} (tolerance {TOL:g})")
+    assert err <= TOL
     # the ordered compensated sums agree with the per-sample values
     y = gpu[:, 0, 0] - gpu[:, 0, 1]
     assert mom[0].count == 1000
