@@ -35,6 +35,24 @@ OPS_PER_CELL_UPDATE = 121.0
 # vector lane-operations per second (256 CUs x 128 lanes x 2.4 GHz).
 VALU_PEAK_OPS = 256 * 128 * 2.4e9
 
+# HBM traffic of the dominant kernel (the 128^2 pair level kernel), from rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE runs of `bench.py --eps 2e-3` (the same kernel at the same full launch
+# size), scaled by what the counters read for a 256 MiB copy (fetch x2.0, write x1.0): a constant
+# per dispatch (the level tables, missed once per XCD) plus bytes per pair (the outputs).  It is
+# reported only while the kernel sources hash to the value the counters were taken on.
+TRAFFIC = {"sha256": None, "fetch_bytes_per_dispatch": None, "write_bytes_per_pair": None,
+           "profile": "profiles/level_kernel_128_pair_hbm_counters.md"}
+KERNEL_SOURCES = ["dk_level.h", "dk_rng.h", "dk_kernels.hip", "dk_internal.h"]
+
+
+def kernel_source_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2311_08872_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -47,12 +65,17 @@ def parse():
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle sampling")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 256 MiB buffer 4 times (reference for HBM byte counters)")
-    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4", "config5"],
-                    help="config2 (default): the bench line; the others print a report line: config3 "
+    ap.add_argument("--workload", default="config2",
+                    choices=["config2", "config2-mc", "config3", "config4", "config5", "paper-type1"],
+                    help="config2 (default): the bench line; the others print a report line: config2-mc "
+                         "plain Monte Carlo on the finest config-2 level to the same eps, config3 "
                          "low-density MLMC with persistent rounds, config4 learned control variate, "
-                         "config5 streaming-kernel throughput at 256^2..1024^2")
+                         "config5 streaming-kernel throughput at 256^2..1024^2, paper-type1 the paper's own "
+                         "Type-1 experiment (MLMC and MC at its accuracies, speed-ups against its table)")
     ap.add_argument("--N", type=float, default=None, help="particle number (config3: 1e5, config5: 1e6)")
     ap.add_argument("--samples", type=int, default=32, help="config5: finest-level pairs to time")
+    ap.add_argument("--cv-levels", default=None, help="config4: comma-separated levels that use the control "
+                                                        "variate (default: those where it lowers variance x cost)")
     return ap.parse_args()
 
 
@@ -118,7 +141,8 @@ def main():
         return
     os.environ.setdefault("DK_LOG", "1")     # progress lines on stderr (per round and per long launch)
     if args.workload != "config2":
-        {"config3": bench_config3, "config4": bench_config4, "config5": bench_config5}[args.workload](args)
+        {"config2-mc": bench_config2_mc, "config3": bench_config3, "config4": bench_config4,
+         "config5": bench_config5, "paper-type1": bench_paper_type1}[args.workload](args)
         return
     base = W.config2(N=1e4)
 
@@ -156,6 +180,9 @@ def main():
     kernel_ms = sum(v["kernel_ms"] for v in stats.values())
     (dl, dc), dom = max(stats.items(), key=lambda kv: kv[1]["kernel_ms"])
     avg_launch_s = dom["kernel_ms"] / 1e3 / dom["launches"]
+    traffic = None
+    if (TRAFFIC["sha256"] and TRAFFIC["sha256"] == kernel_source_sha256() and (dl, dc) == (base.levels - 1, True)):
+        traffic = TRAFFIC["fetch_bytes_per_dispatch"] + TRAFFIC["write_bytes_per_pair"] * dom["samples"] / dom["launches"]
     ops_per_launch = OPS_PER_CELL_UPDATE * dom["cell_updates"] / dom["launches"]
     achieved = ops_per_launch / avg_launch_s
     last = results[-1]
@@ -195,7 +222,8 @@ def main():
                                "speedup_vs_mlmc": mc_M * mc_sample_s / per_step if per_step > 0 else None},
         "roofline": {"bound": "alu", "kernel": f"level_kernel pair={dc} level={dl} ({base.n(dl)}^2)",
                      "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12, "unit": "Top/s",
-                     "frac": achieved / VALU_PEAK_OPS, "traffic": None,
+                     "frac": achieved / VALU_PEAK_OPS, "traffic": traffic,
+                     "traffic_unit": "bytes per launch (HBM, rocprofv3 counters)",
                      "ops_per_cell_update": OPS_PER_CELL_UPDATE,
                      "cell_updates_per_launch": dom["cell_updates"] / dom["launches"],
                      "avg_launch_ms": avg_launch_s * 1e3,
@@ -213,6 +241,83 @@ def _report(workload, value, unit, extra):
             "config": {"workload": workload}, "report_only": True}
     line.update(extra)
     print(json.dumps(line), flush=True)
+
+
+def bench_config2_mc(args):
+    """Plain Monte Carlo (the paper's comparison estimator) on the finest config-2 level (128^2,
+    8192 steps, single paths from their own noise stream) to RMSE args.eps: a pilot of 1000 paths,
+    then M = ceil(2 Var / eps^2) paths, so that the variance term meets eps^2 / 2 as in the MLMC
+    run.  Measured, not projected."""
+    import torch
+    import dk_workloads as W
+    import paper_2311_08872_amd as dk
+    p = W.config2(N=1e4)
+    L = p.levels - 1
+    ctx = dk.Context(0)
+    dk.estimate(p.with_(seed=1000), 5e-2, ctx=ctx, plain_mc_level=L)       # warm-up (untimed)
+    ctx.close()
+    ctx = dk.Context(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = dk.estimate(p, args.eps, ctx=ctx, plain_mc_level=L)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = ctx.stats()
+    ctx.close()
+    _report(f"config-2 plain MC on the finest level (128^2, 8192 steps), eps={args.eps:g}", wall, "s",
+            {"mc": {"level": L, "M": r["M"][L], "estimate": r["estimate"][p.primary], "var_est": r["var_est"][0],
+                    "rmse_est": r["rmse_est"], "rounds": r["rounds"], "cell_updates": r["cell_updates"]},
+             "cell_updates_per_s": r["cell_updates"] / wall,
+             "kernels": [{k: s_[k] for k in ("level", "coupled", "launches", "samples", "kernel_ms", "cell_updates", "rows")}
+                         for s_ in st]})
+
+
+def bench_paper_type1(args):
+    """The paper's Type-1 experiment (Sec. 7) in its own setting: the 2 pi torus, h_l = 2 pi
+    2^-(2+l) (4^2 .. 128^2), tau_l = 1e-3 4^(5-l), T = 1.024, phi = sin x + sin y, psi = x^2, the
+    regular datum at N = 2e9 and 2e5 and the irregular one at N = 2e9.  For every accuracy of its
+    list, Algorithm 1, then plain MC on the finest level that run reached, to the same variance
+    target (eps^2 / 2).  Both are measured (not extrapolated).  Speed-ups are reported as the ratio
+    of wall times on this GPU and as the ratio of work (fine + coarse cell updates), the latter
+    comparable with the paper's CPU timings; the paper's table gives 5.6, 5.4 and 22.8 at the
+    smallest accuracies."""
+    import torch
+    import dk_workloads as W
+    import paper_2311_08872_amd as dk
+    reg = [10 ** -1.4, 10 ** -1.7, 10 ** -2.0, 10 ** -2.2, 10 ** -2.4, 10 ** -2.6]
+    irreg = reg[:-1] + [10 ** -2.75]
+    settings = [("reg", 2e9, W.paper_reg, reg, 5.6), ("reg", 2e5, W.paper_reg, reg, 5.4),
+                ("irreg", 2e9, W.paper_irreg, irreg, 22.8)]
+    ctx = dk.Context(0)
+    dk.estimate(W.paper_reg(2e9).with_(seed=1000), 10 ** -1.4, ctx=ctx)         # warm-up (untimed)
+    ctx.close()
+    for name, N, make, eps_list, paper_speedup in settings:
+        p = make(N)
+        rows = []
+        for eps in eps_list:
+            ctx = dk.Context(0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = dk.estimate(p, eps, ctx=ctx)
+            torch.cuda.synchronize()
+            t_mlmc = time.perf_counter() - t0
+            L = r["L"]
+            t0 = time.perf_counter()
+            mc = dk.estimate(p.with_(seed=p.seed + 1), eps, ctx=ctx, plain_mc_level=L)
+            torch.cuda.synchronize()
+            t_mc = time.perf_counter() - t0
+            ctx.close()
+            rows.append({"eps": eps, "L": L, "converged": r["converged"], "M": r["M"], "estimate": r["estimate"][0],
+                         "Yhat": r["Yhat"], "Vhat": r["Vhat"], "mlmc_s": t_mlmc, "mlmc_cell_updates": r["cell_updates"],
+                         "mc_M": mc["M"][L], "mc_s": t_mc, "mc_cell_updates": mc["cell_updates"],
+                         "speedup_wall": t_mc / t_mlmc, "speedup_work": mc["cell_updates"] / r["cell_updates"]})
+            print(f"[bench] paper {name} N={N:g} eps={eps:.3g}: L={L} MLMC {t_mlmc:.3f} s, MC {t_mc:.3f} s, "
+                  f"work ratio {rows[-1]['speedup_work']:.2f}", file=sys.stderr, flush=True)
+        last = rows[-1]
+        _report(f"paper Sec. 7 Type-1 experiment: rho0_{name}, N={N:g}, 2 pi torus, h=2pi/4..2pi/128, "
+                f"tau_l=1e-3*4^(5-l), T=1.024", last["speedup_work"], "MC/MLMC work ratio at the smallest eps",
+                {"paper_speedup_at_smallest_eps": paper_speedup, "smallest_eps": last["eps"], "L_reached": last["L"],
+                 "speedup_wall_at_smallest_eps": last["speedup_wall"], "runs": rows})
 
 
 def bench_config3(args):
@@ -274,14 +379,17 @@ def bench_config3(args):
 
 def bench_config4(args):
     """Learned control variate (config 4): for every pair l >= 1 of config 2, a network trained on
-    2^16 pairs from its own noise stream, then Algorithm 1 to args.eps with the control variate on
-    levels 1..4 (4 independent coarse-only paths per pair).  Wall time includes the training.
-    Reports each network's held-out variance ratio Var(Y - r) / Var(Y)."""
+    2^16 pairs from its own noise stream; its held-out statistics decide whether level l uses it:
+    the control-variate sample Z = (Y - r) + mean of r over k = 4 independent coarse-only paths has
+    variance Var(Y - r) + Var(r) / k and costs (1 + k / 17) pairs, so the level uses it only if
+    (Var(Y - r) + Var(r) / k) (1 + k / 17) < Var(Y) (--cv-levels forces a set).  Then Algorithm
+    1 to args.eps.  Wall time includes the training."""
     import numpy as np
     import torch
     import dk_workloads as W
     import paper_2311_08872_amd as dk
     p = W.config2(N=1e4)
+    kappa = 4
     ctx = dk.Context(0)
     dk.estimate(p.with_(seed=1000), 2e-2, ctx=ctx)                      # warm-up (untimed)
     ctx.close()
@@ -290,21 +398,31 @@ def bench_config4(args):
     t0 = time.perf_counter()
     params = np.zeros((p.levels, dk.L.DK_CNN_NPARAM), np.float32)
     train = {}
+    use = []
     for l in range(1, p.levels):
         t1 = time.perf_counter()
         res = dk.cv_train(p, l, n_train=1 << 16, epochs=6, batch=256, lr=1e-3, n_val=1 << 13, seed=l, ctx=ctx)
         params[l] = res["params"]
+        var_z = res["var_Y_minus_r"] + res["var_r"] / kappa
+        gain = res["var_Y"] / (var_z * (1 + kappa / 17))
         train[l] = {"s": time.perf_counter() - t1, "var_Y": res["var_Y"], "var_Y_minus_r": res["var_Y_minus_r"],
-                    "var_r": res["var_r"], "ratio": res["var_Y_minus_r"] / res["var_Y"]}
-        print(f"[bench] config4 level {l} trained: ratio {train[l]['ratio']:.4f}", file=sys.stderr, flush=True)
+                    "var_r": res["var_r"], "explained": 1 - res["var_Y_minus_r"] / res["var_Y"],
+                    "variance_cost_gain": gain}
+        if gain > 1:
+            use.append(l)
+        print(f"[bench] config4 level {l} trained: explained {train[l]['explained']:.4f}, gain {gain:.3f}",
+              file=sys.stderr, flush=True)
+    if args.cv_levels is not None:
+        use = [int(v) for v in args.cv_levels.split(",") if v]
+    mask = sum(1 << l for l in use)
     t_train = time.perf_counter() - t0
-    r = dk.estimate(p, args.eps, ctx=ctx, cv_params=params, cv_level_mask=0b11110, cv_ratio=4)
+    r = dk.estimate(p, args.eps, ctx=ctx, cv_params=params, cv_level_mask=mask, cv_ratio=kappa)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ctx.close()
-    _report(f"config-4 learned control variate on config-2 pairs l=1..4 (2^16 training pairs per level), "
-            f"eps={args.eps:g}", wall, "s",
-            {"train_s": t_train, "train": train,
+    _report(f"config-4 learned control variate on config-2 pairs l=1..4 (2^16 training pairs per level, "
+            f"used on levels {use}), eps={args.eps:g}", wall, "s",
+            {"train_s": t_train, "train": train, "cv_levels": use,
              "mlmc": {k: r[k] for k in ("L", "converged", "M", "Yhat", "Vhat", "rmse_est", "rounds", "cell_updates")}})
 
 

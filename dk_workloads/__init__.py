@@ -210,15 +210,44 @@ def config5(N: float = 1e6) -> Problem:
                    obs=config2_obs()[:1], primary=0, seed=0)
 
 
-def paper_reg(N: float = 2e9) -> Problem:
-    """The paper's Sec. 7 setting with the regular initial datum (2 pi torus, h_l = 2 pi 2^-(2+l),
-    tau_l = 1e-3 4^(5-l), T = 1.024, phi = sin x + sin y, psi = x^2).  The normalising constant is
-    left at 1 here; callers that want int rho0 = 1 set es_scale."""
+def _bessel_i0(x: float) -> float:
+    """Modified Bessel function I_0 by its power series sum_k (x/2)^(2k) / (k!)^2."""
+    term, total, k = 1.0, 1.0, 0
+    while term > 1e-17 * total:
+        k += 1
+        term *= (x / 2.0) ** 2 / (k * k)
+        total += term
+    return total
+
+
+def _expsin2_mass(a: float, b: float, s: float) -> float:
+    """Integral over (0, 2 pi)^2 of a + b exp(-(sin^2(x - x0) + sin^2(y - y0)) / (2 s)): with
+    sin^2 = (1 - cos 2x)/2 each axis gives 2 pi exp(-1/(4s)) I_0(1/(4s))."""
+    two_pi = 2.0 * math.pi
+    axis = two_pi * math.exp(-1.0 / (4.0 * s)) * _bessel_i0(1.0 / (4.0 * s))
+    return a * two_pi * two_pi + b * axis * axis
+
+
+def _paper_problem(N: float, a: float, b: float, s: float) -> Problem:
+    """The paper's Sec. 7 setting: the 2 pi torus, h_l = 2 pi 2^-(2+l) (4 x 4 .. 128 x 128, six
+    levels), tau_l = 1e-3 4^(5-l) (constant tau/h^2 = 1.024/(pi/2)^2 ~ 0.415), T = 1.024,
+    phi = sin x + sin y, psi = x^2 of the centred, sqrt(N)-scaled observable, and the initial
+    datum normalised to unit mass."""
     two_pi = 2.0 * math.pi
     h5 = two_pi / 128.0
     mu = 1e-3 / (h5 * h5)
-    rho0 = Field(FIELD_EXPSIN2, es_a=1.0, es_b=1.0 / math.sqrt(two_pi), es_s=1.0,
-                 es_x0=0.5 * math.pi, es_y0=1.5 * math.pi, es_scale=1.0)
+    rho0 = Field(FIELD_EXPSIN2, es_a=a, es_b=b, es_s=s, es_x0=0.5 * math.pi, es_y0=1.5 * math.pi,
+                 es_scale=1.0 / _expsin2_mass(a, b, s))
     phi = Field(FIELD_MODES, 0.0, [sin_mode(1, 0), sin_mode(0, 1)])
     return Problem(box=two_pi, n0=4, levels=6, mu=mu, T=1.024, N=N, steps_policy=STEPS_ROUND_T,
                    rho0=rho0, obs=[Obs(phi, True, True, PSI_SQUARE)], primary=0, seed=0)
+
+
+def paper_reg(N: float = 2e9) -> Problem:
+    """Sec. 7 with the regular datum Z^-1 (1 + exp(-(sin^2(x - pi/2) + sin^2(y - 3 pi/2))/2) / sqrt(2 pi))."""
+    return _paper_problem(N, 1.0, 1.0 / math.sqrt(2.0 * math.pi), 1.0)
+
+
+def paper_irreg(N: float = 2e9) -> Problem:
+    """Sec. 7 with the irregular datum Z^-1 exp(-(sin^2(x - pi/2) + sin^2(y - 3 pi/2))/(2 * 0.1))."""
+    return _paper_problem(N, 0.0, 1.0, 0.1)

@@ -38,6 +38,7 @@ level_kernel(const LevelArgs A)
 int shape_rows(int nf, int v)
 {
     switch (nf) {
+        case 4: return v == 0 ? 4 : 0;
         case 8: { const int r[] = {8, 2, 4}; return v < 3 ? r[v] : 0; }
         case 16: { const int r[] = {8, 4, 2}; return v < 3 ? r[v] : 0; }
         case 32: { const int r[] = {8, 4, 16}; return v < 3 ? r[v] : 0; }
@@ -64,7 +65,10 @@ static hipError_t launch_variants(const LevelArgs& A, int v, hipStream_t s)
 {
     constexpr bool TUNED = std::is_same<Real, float>::value && NOISE;
     if (!TUNED) v = 0;
-    if constexpr (NF == 8) {
+    if constexpr (NF == 4) {
+        // 4 x 4 (the level 0 of the paper's own hierarchy): 2 lanes per sample, 4 rows each
+        return launch_R<Real, 4, 4, PAIR, FLUX, NOISE>(A, s);
+    } else if constexpr (NF == 8) {
         if constexpr (TUNED) {
             if (v == 1) return launch_R<Real, 8, 2, PAIR, FLUX, NOISE>(A, s);
             if (v == 2) return launch_R<Real, 8, 4, PAIR, FLUX, NOISE>(A, s);
@@ -102,6 +106,7 @@ template <typename Real, bool PAIR, int FLUX, bool NOISE>
 static hipError_t launch_nf(const LevelArgs& A, int v, hipStream_t s)
 {
     switch (A.nf) {
+        case 4: return launch_variants<Real, 4, PAIR, FLUX, NOISE>(A, v, s);
         case 8: return launch_variants<Real, 8, PAIR, FLUX, NOISE>(A, v, s);
         case 16: return launch_variants<Real, 16, PAIR, FLUX, NOISE>(A, v, s);
         case 32: return launch_variants<Real, 32, PAIR, FLUX, NOISE>(A, v, s);
@@ -111,7 +116,7 @@ static hipError_t launch_nf(const LevelArgs& A, int v, hipStream_t s)
     }
 }
 
-bool level_supported(int nf) { return nf == 8 || nf == 16 || nf == 32 || nf == 64 || nf == 128; }
+bool level_supported(int nf) { return nf == 4 || nf == 8 || nf == 16 || nf == 32 || nf == 64 || nf == 128; }
 
 hipError_t launch_level(const LevelKind& k, const LevelArgs& A, hipStream_t s)
 {

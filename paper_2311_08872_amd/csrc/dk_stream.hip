@@ -111,20 +111,21 @@ __global__ void __launch_bounds__(THREADS, 4) stream_kernel(const StreamArgs A)
                     Z[k][1] += (w1[0] + w1[1]) + (w1[2] + w1[3]);
                 }
             }
+            // fluxes of all 4 cells: those outside this step's region get values no valid update reads
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int ex = 2 * bx + (q & 1), ey = 2 * by + (q >> 1);
-                if (ex < j || ex >= EXT - j || ey < j || ey >= EXT - j) continue;
-                const float rv = sr[ey * EXT + ex];
+                const int c = ey * EXT + ex;
+                const float rv = sr[c];
                 if (FLUX == DK_FLUX_CENTRAL) {
                     const float sq = psq(rv);
-                    sf0[ey * EXT + ex] = sq * w0[q];
-                    sf1[ey * EXT + ex] = sq * w1[q];
+                    sf0[c] = sq * w0[q];
+                    sf1[c] = sq * w1[q];
                 } else {
-                    const float rx = ex + 1 < EXT ? sr[ey * EXT + ex + 1] : rv;
-                    const float ry = ey + 1 < EXT ? sr[(ey + 1) * EXT + ex] : rv;
-                    sf0[ey * EXT + ex] = psq(0.5f * (rv + rx)) * w0[q];
-                    sf1[ey * EXT + ex] = psq(0.5f * (rv + ry)) * w1[q];
+                    const float rx = sr[ex + 1 < EXT ? c + 1 : c];
+                    const float ry = sr[ey + 1 < EXT ? c + EXT : c];
+                    sf0[c] = psq(0.5f * (rv + rx)) * w0[q];
+                    sf1[c] = psq(0.5f * (rv + ry)) * w1[q];
                 }
             }
         }

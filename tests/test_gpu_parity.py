@@ -39,7 +39,7 @@ def banner(msg):
 
 @pytest.mark.parametrize("level,n,samples,steps,first_sample,tag", [
     (0, 8, 3, 5, 0, 0), (2, 32, 2, 3, 17, 0), (4, 128, 1, 2, 5, 1), (1, 16, 2, 4, (1 << 32) + 7, 0),
-    (3, 6, 2, 3, 0, 3)])
+    (3, 6, 2, 3, 0, 3), (0, 4, 4, 3, 9, 0)])
 def test_noise_bit_identical(level, n, samples, steps, first_sample, tag):
     banner(f"noise level={level} n={n} samples={samples} first={first_sample} tag={tag}")
     seed = 0x1234_5678_9ABC
@@ -58,6 +58,25 @@ def test_meanfield_centring_constants():
         c = dk.meanfield(p, level)
         ref = op.centre(level)
         assert np.allclose(c, ref, rtol=1e-12, atol=1e-14), (level, c, ref)
+
+
+@pytest.mark.parametrize("make", [W.paper_reg, W.paper_irreg])
+@pytest.mark.parametrize("level,count", [(0, 300), (1, 200), (2, 100), (3, 40), (4, 8)])
+def test_paper_setting_per_sample_parity(make, level, count):
+    """The paper's Sec. 7 hierarchy from 4 x 4 (2 lanes per sample, 4 rows each) up to 64 x 64,
+    both initial data, N = 2e5: per-sample observables against the oracle; the centring
+    constants of every level against the oracle's mean field."""
+    p = make(N=2e5)
+    banner(f"{make.__name__} level={level} count={count} (nf={p.n(level)}, steps={p.steps(level)})")
+    c = dk.meanfield(p, level)
+    assert np.allclose(c, oracle.OracleProblem(p).centre(level), rtol=1e-12, atol=1e-14)
+    _, ps = dk.level_pair(p, level, 0, count, per_sample=True)
+    torch.cuda.synchronize()
+    gpu = ps.cpu().numpy()
+    ref = oracle.run_range(oracle.OracleProblem(p), level, 0, count)
+    err = scaled_err(gpu, ref)
+    banner(f"scaled FP32-vs-FP64 error {err:.3g} (tolerance {TOL:g})")
+    assert err <= TOL
 
 
 @pytest.mark.parametrize("level,count", [(0, 200), (1, 150), (2, 70), (3, 16)])
