@@ -66,12 +66,13 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 256 MiB buffer 4 times (reference for HBM byte counters)")
     ap.add_argument("--workload", default="config2",
-                    choices=["config2", "config2-mc", "config3", "config4", "config5", "paper-type1"],
+                    choices=["config2", "config2-mc", "config3", "config4", "config5", "paper-type1", "paper-type2"],
                     help="config2 (default): the bench line; the others print a report line: config2-mc "
                          "plain Monte Carlo on the finest config-2 level to the same eps, config3 "
                          "low-density MLMC with persistent rounds, config4 learned control variate, "
                          "config5 streaming-kernel throughput at 256^2..1024^2, paper-type1 the paper's own "
-                         "Type-1 experiment (MLMC and MC at its accuracies, speed-ups against its table)")
+                         "Type-1 experiment (MLMC and MC at its accuracies, speed-ups against its table), "
+                         "paper-type2 its variance-reduction factor against h_min")
     ap.add_argument("--N", type=float, default=None, help="particle number (config3: 1e5, config5: 1e6)")
     ap.add_argument("--samples", type=int, default=32, help="config5: finest-level pairs to time")
     ap.add_argument("--cv-levels", default=None, help="config4: comma-separated levels that use the control "
@@ -142,7 +143,8 @@ def main():
     os.environ.setdefault("DK_LOG", "1")     # progress lines on stderr (per round and per long launch)
     if args.workload != "config2":
         {"config2-mc": bench_config2_mc, "config3": bench_config3, "config4": bench_config4,
-         "config5": bench_config5, "paper-type1": bench_paper_type1}[args.workload](args)
+         "config5": bench_config5, "paper-type1": bench_paper_type1,
+         "paper-type2": bench_paper_type2}[args.workload](args)
         return
     base = W.config2(N=1e4)
 
@@ -318,6 +320,53 @@ def bench_paper_type1(args):
                 f"tau_l=1e-3*4^(5-l), T=1.024", last["speedup_work"], "MC/MLMC work ratio at the smallest eps",
                 {"paper_speedup_at_smallest_eps": paper_speedup, "smallest_eps": last["eps"], "L_reached": last["L"],
                  "speedup_wall_at_smallest_eps": last["speedup_wall"], "runs": rows})
+
+
+def bench_paper_type2(args):
+    """The paper's Type-2 experiment (Sec. 7, Prop. PropVarFactor): MLMC with the fixed geometric
+    schedule M_(l-1) = 4 M_l (M_L = args.samples * 32 on the finest level) for h_min = 2 pi 2^-(2+L),
+    L = 1..5.  From the per-level moments: the MLMC estimator's variance sum_l V_l / M_l and cost
+    sum_l M_l C_l, and the variance of plain MC on the finest level at the same cost,
+    Var(P_L) C_L / cost.  Their ratio F is compared with the proposition's NN rate
+    [(N h_min^2)^-1 + h_min^2]^-1 |log h_min|^-1 (up to a constant, reported normalised to L = 1)."""
+    import torch
+    import dk_workloads as W
+    import paper_2311_08872_amd as dk
+    settings = [("reg", 2e9, W.paper_reg), ("reg", 2e5, W.paper_reg), ("irreg", 2e9, W.paper_irreg)]
+    m_top = args.samples * 32
+    for name, N, make in settings:
+        p = make(N)
+        rows = []
+        for L in range(1, p.levels):
+            count = [m_top * 4 ** (L - l) for l in range(L + 1)]
+            ctx = dk.Context(0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            mom = dk.round_sums(p.with_(seed=p.seed + L), L, [0] * (L + 1), count, ctx=ctx)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            ctx.close()
+            V, C = [], []
+            for l in range(L + 1):
+                m = mom[l][p.primary]
+                n = m.count
+                V.append(max(0.0, (m.sums[1] - m.sums[0] ** 2 / n) / (n - 1)))
+                C.append(p.n(l) ** 2 * p.steps(l) * (1.0 + (l > 0) / 16.0))
+            mL = mom[L][p.primary]
+            var_PL = max(0.0, (mL.sums[3] - mL.sums[2] ** 2 / mL.count) / (mL.count - 1))
+            var_ml = sum(V[l] / count[l] for l in range(L + 1))
+            cost = sum(count[l] * C[l] for l in range(L + 1))
+            c_single = p.n(L) ** 2 * p.steps(L)
+            var_mc = var_PL * c_single / cost
+            h = p.box / p.n(L)
+            rate = 1.0 / ((1.0 / (N * h * h) + h * h) * abs(math.log(h)))
+            rows.append({"L": L, "h_min": h, "M": count, "V": V, "var_P_L": var_PL, "var_mlmc": var_ml,
+                         "var_mc_same_cost": var_mc, "F": var_mc / var_ml, "rate": rate, "wall_s": wall})
+        for r in rows:
+            r["rate_normalised"] = r["rate"] / rows[0]["rate"] * rows[0]["F"]
+        print(f"[bench] paper type2 {name} N={N:g}: F = {[round(r['F'], 2) for r in rows]}", file=sys.stderr, flush=True)
+        _report(f"paper Sec. 7 Type-2 experiment: rho0_{name}, N={N:g}, M_(l-1) = 4 M_l, M_L = {m_top}",
+                rows[-1]["F"], "variance-reduction factor F at h_min = 2 pi/128", {"rows": rows})
 
 
 def bench_config3(args):
