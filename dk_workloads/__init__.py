@@ -232,7 +232,9 @@ def _paper_problem(N: float, a: float, b: float, s: float) -> Problem:
     """The paper's Sec. 7 setting: the 2 pi torus, h_l = 2 pi 2^-(2+l) (4 x 4 .. 128 x 128, six
     levels), tau_l = 1e-3 4^(5-l) (constant tau/h^2 = 1.024/(pi/2)^2 ~ 0.415), T = 1.024,
     phi = sin x + sin y, psi = x^2 of the centred, sqrt(N)-scaled observable, and the initial
-    datum normalised to unit mass."""
+    datum normalised to unit mass.  The state is FP64: at N = 2e9 the density of a fine cell
+    fluctuates by ~1e-4 of itself, so binary32 rounding of the state alone would be ~1e-3 of the
+    centred, sqrt(N)-scaled observable."""
     two_pi = 2.0 * math.pi
     h5 = two_pi / 128.0
     mu = 1e-3 / (h5 * h5)
@@ -240,7 +242,7 @@ def _paper_problem(N: float, a: float, b: float, s: float) -> Problem:
                  es_scale=1.0 / _expsin2_mass(a, b, s))
     phi = Field(FIELD_MODES, 0.0, [sin_mode(1, 0), sin_mode(0, 1)])
     return Problem(box=two_pi, n0=4, levels=6, mu=mu, T=1.024, N=N, steps_policy=STEPS_ROUND_T,
-                   rho0=rho0, obs=[Obs(phi, True, True, PSI_SQUARE)], primary=0, seed=0)
+                   rho0=rho0, obs=[Obs(phi, True, True, PSI_SQUARE)], primary=0, seed=0, precision=PREC_F64)
 
 
 def paper_reg(N: float = 2e9) -> Problem:
