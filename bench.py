@@ -40,7 +40,8 @@ VALU_PEAK_OPS = 256 * 128 * 2.4e9
 # size), scaled by what the counters read for a 256 MiB copy (fetch x2.0, write x1.0): a constant
 # per dispatch (the level tables, missed once per XCD) plus bytes per pair (the outputs).  It is
 # reported only while the kernel sources hash to the value the counters were taken on.
-TRAFFIC = {"sha256": None, "fetch_bytes_per_dispatch": None, "write_bytes_per_pair": None,
+TRAFFIC = {"sha256": "f2e4ee90aec607d2afd1ee4f3623dab1c34fa32b87c5f80b52820443bbb2577e",
+           "fetch_bytes_per_dispatch": 1730.0 * 1024 * 2.0, "write_bytes_per_pair": 32.0 * 1.0,
            "profile": "profiles/level_kernel_128_pair_hbm_counters.md"}
 KERNEL_SOURCES = ["dk_level.h", "dk_rng.h", "dk_kernels.hip", "dk_internal.h"]
 
