@@ -77,6 +77,9 @@ extern "C" {
 #define DK_TAG_CV_TRAIN 2     /* training pairs of the control variate              */
 #define DK_TAG_CV_COARSE 3    /* independent coarse-only paths of the control variate */
 
+#define DK_COST_CELLS 0       /* dk_mlmc_opts.cost_model: cell updates per sample (deterministic) */
+#define DK_COST_MEASURED 1    /*                          measured kernel seconds per sample      */
+
 #define DK_CNN_NPARAM 5953    /* parameters of the control-variate network */
 
 #define DK_MAX_OBS 64
@@ -160,7 +163,14 @@ typedef struct {
                                  Modes 0-2 give identical results; mode 3 uses 8 rows per lane and
                                  sums moments per task, so its results agree with mode 0's to
                                  rounding (per-sample paths are the same).                         */
-    int32_t reserved;
+    int32_t cost_model;       /* DK_COST_CELLS (0, default): C_l = fine + coarse cell updates per
+                                 sample, so the M_l are a function of the samples alone;
+                                 DK_COST_MEASURED (1): C_l = measured kernel seconds per sample of
+                                 level l (HIP events of the previous rounds; levels not yet run use
+                                 the cell count scaled by the last measured level's time per cell
+                                 update).  Faster levels then get more samples; the M_l depend on
+                                 timings.  Rounds whose kernels are not timed per level (the
+                                 persistent round, round_mode 3) keep the cell model.            */
     const char* checkpoint_path; /* NULL, or a file for Algorithm-1 checkpoints: after every round
                                  the state (levels, samples done and targeted, compensated sums) is
                                  written to path.tmp and renamed over path.  A run that finds the
@@ -181,7 +191,8 @@ typedef struct {
     uint64_t M[DK_MAX_LEVELS];     /* samples per level                                          */
     double Yhat[DK_MAX_LEVELS];    /* mean of Y_l, primary observable                            */
     double Vhat[DK_MAX_LEVELS];    /* unbiased variance of Y_l, primary observable               */
-    double cost[DK_MAX_LEVELS];    /* C_l = cell updates per sample                              */
+    double cost[DK_MAX_LEVELS];    /* C_l used by the last round: cell updates per sample, or
+                                      seconds per sample with DK_COST_MEASURED                   */
     double cell_updates;           /* total fine + coarse cell updates performed                 */
     double wall_s;                 /* host wall time of the call                                 */
 } dk_mlmc_result;

@@ -228,7 +228,7 @@ def round_sums(problem, finest: int, first, count, tag: int = W.TAG_MLMC, round_
 
 
 def _opts(m_pilot=1000, L_start=2, alpha=2.0, max_rounds=1000, plain_mc_level=-1, max_samples=0, cv_params=None,
-          cv_level_mask=0, cv_ratio=4, round_mode=0, checkpoint_path=None, _keep=None):
+          cv_level_mask=0, cv_ratio=4, round_mode=0, checkpoint_path=None, cost_model=0, _keep=None):
     ptr = None
     if cv_params is not None:
         arr = np.ascontiguousarray(cv_params, dtype=np.float32)
@@ -241,7 +241,7 @@ def _opts(m_pilot=1000, L_start=2, alpha=2.0, max_rounds=1000, plain_mc_level=-1
         if _keep is not None:
             _keep.append(ck)
     return L.dk_mlmc_opts(m_pilot, L_start, alpha, max_rounds, plain_mc_level, max_samples, ptr, cv_level_mask,
-                          cv_ratio, round_mode, 0, ck)
+                          cv_ratio, round_mode, cost_model, ck)
 
 
 def _result_dict(r: L.dk_mlmc_result, nobs: int, rc: int) -> dict:

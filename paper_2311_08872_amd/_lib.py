@@ -45,7 +45,7 @@ class dk_mlmc_opts(C.Structure):
     _fields_ = [("m_pilot", C.c_int32), ("L_start", C.c_int32), ("alpha", C.c_double), ("max_rounds", C.c_int32),
                 ("plain_mc_level", C.c_int32), ("max_samples", C.c_uint64), ("cv_params", C.POINTER(C.c_float)),
                 ("cv_level_mask", C.c_uint32), ("cv_ratio", C.c_int32), ("round_mode", C.c_int32),
-                ("reserved", C.c_int32), ("checkpoint_path", C.c_char_p)]
+                ("cost_model", C.c_int32), ("checkpoint_path", C.c_char_p)]
 
 
 class dk_mlmc_result(C.Structure):

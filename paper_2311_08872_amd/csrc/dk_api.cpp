@@ -1106,7 +1106,7 @@ uint64_t alg1_key(double eps, int L_max, const double* cost, const dk_mlmc_opts&
     Fnv f;
     f.val(eps); f.val(L_max);
     for (int l = 0; l <= L_max; ++l) f.val(cost[l]);
-    f.val(o.m_pilot); f.val(o.L_start); f.val(o.alpha); f.val(o.max_samples);
+    f.val(o.m_pilot); f.val(o.L_start); f.val(o.alpha); f.val(o.max_samples); f.val(o.cost_model);
     return f.h;
 }
 
@@ -1194,14 +1194,21 @@ int read_checkpoint(const char* path, uint64_t key, int levels, Alg1State& S)
 // optional: all levels of one round at once; sums [L+1][2]
 typedef int (*round_sampler)(void* user, int L, const uint64_t* first, const uint64_t* count, double* sums);
 
+// measure(L, C): optional; with DK_COST_MEASURED it replaces C[0..L] by measured costs after a round
+typedef std::function<void(int, std::vector<double>&)> cost_measure;
+
 int alg1_core(double eps, int L_max, const double* cost, const dk_mlmc_opts& o, dk_level_sampler sampler, void* user,
-              dk_mlmc_result* out, round_sampler rsampler = nullptr, const CkptHooks* ck = nullptr)
+              dk_mlmc_result* out, round_sampler rsampler = nullptr, const CkptHooks* ck = nullptr,
+              const cost_measure* measure = nullptr)
 {
     if (!(eps > 0)) return fail(DK_EINVAL, "eps must be > 0");
     if (L_max < 0 || L_max >= DK_MAX_LEVELS) return fail(DK_EINVAL, "L_max out of range");
     if (o.m_pilot < 2) return fail(DK_EINVAL, "m_pilot must be >= 2");
     for (int l = 0; l <= L_max; ++l)
         if (!(cost[l] > 0)) return fail(DK_EINVAL, "cost[%d] must be > 0", l);
+    if (o.cost_model != DK_COST_CELLS && o.cost_model != DK_COST_MEASURED)
+        return fail(DK_EINVAL, "cost_model must be DK_COST_CELLS or DK_COST_MEASURED");
+    std::vector<double> C(cost, cost + L_max + 1);   // costs in use (measured ones replace these)
     int L = std::min(std::max(o.L_start, 0), L_max);
     std::vector<uint64_t> done(L_max + 1, 0), target(L_max + 1, 0);
     std::vector<double> s1(L_max + 1, 0), c1(L_max + 1, 0), s2(L_max + 1, 0), c2(L_max + 1, 0);
@@ -1288,10 +1295,11 @@ int alg1_core(double eps, int L_max, const double* cost, const dk_mlmc_opts& o, 
             std::fprintf(stderr, "\n");
             std::fflush(stderr);
         }
+        if (o.cost_model == DK_COST_MEASURED && measure && *measure) (*measure)(L, C);
         double acc = 0.0;
-        for (int l = 0; l <= L; ++l) acc += std::sqrt(V[l] * cost[l]);
+        for (int l = 0; l <= L; ++l) acc += std::sqrt(V[l] * C[l]);
         for (int l = 0; l <= L; ++l) {
-            const double m = std::ceil(2.0 / (eps * eps) * std::sqrt(V[l] / cost[l]) * acc);
+            const double m = std::ceil(2.0 / (eps * eps) * std::sqrt(V[l] / C[l]) * acc);
             uint64_t mi = m > 1.8e19 ? (uint64_t)1.8e19 : (uint64_t)m;
             if (o.max_samples && mi > o.max_samples) mi = o.max_samples;
             target[l] = std::max(done[l], mi);
@@ -1312,7 +1320,7 @@ int alg1_core(double eps, int L_max, const double* cost, const dk_mlmc_opts& o, 
         out->M[l] = done[l];
         out->Yhat[l] = Y[l];
         out->Vhat[l] = V[l];
-        out->cost[l] = cost[l];
+        out->cost[l] = C[l];
         est += Y[l];
         var += V[l] / (double)done[l];
     }
@@ -2080,8 +2088,32 @@ int dk_mlmc_estimate(dk_context* ctx, const dk_problem* problem, double eps, con
             for (dk_moments& m : G.zmom) get(m);
             return DK_OK;
         };
+        // measured costs: kernel seconds per sample of each level since this call began
+        std::map<std::pair<int, int>, KStat> base = ctx->stats;
+        cost_measure measure = [&](int L, std::vector<double>& C) {
+            int ref = -1;
+            double ref_per_cell = 0;
+            std::vector<bool> got(L + 1, false);
+            for (int l = 0; l <= L; ++l) {
+                if ((G.cv_mask >> l) & 1u) continue;   // control-variate levels keep the cell model
+                const auto key = std::make_pair(l, l >= 1 && !G.plain_mc ? 1 : 0);
+                const KStat now = ctx->stats.count(key) ? ctx->stats[key] : KStat{};
+                const KStat b = base.count(key) ? base[key] : KStat{};
+                const double ms = now.ms - b.ms;
+                const uint64_t n = now.samples - b.samples;
+                if (n > 0 && ms > 0) {
+                    C[l] = ms * 1e-3 / (double)n;
+                    got[l] = true;
+                    ref = l;
+                    ref_per_cell = C[l] / cost[l];
+                }
+            }
+            if (ref < 0) { for (int l = 0; l <= L; ++l) C[l] = cost[l]; return; }
+            for (int l = 0; l <= L; ++l)
+                if (!got[l]) C[l] = cost[l] * ref_per_cell;
+        };
         rc = alg1_core(eps, problem->levels - 1, cost.data(), o, gpu_sample, &G, out,
-                       o.round_mode > 0 ? gpu_round : nullptr, &ck);
+                       o.round_mode > 0 ? gpu_round : nullptr, &ck, &measure);
         if (rc < 0) return rc;
     } else {
         // plain MC on one level: pilot, then M = ceil(2 V / eps^2) so that V / M <= eps^2 / 2

@@ -150,3 +150,22 @@ def test_checkpoint_resume_is_bit_identical(tmp_path, mode):
     for a, b in zip(res["level_moments"], full["level_moments"]):
         for ma, mb in zip(a, b):
             assert ma.count == mb.count and (ma.sums == mb.sums).all()
+
+
+def test_measured_cost_model():
+    """DK_COST_MEASURED: Algorithm 1 weighs levels by their measured kernel seconds per sample;
+    the costs it reports are seconds per sample that grow with the level (17-fold per level in
+    cell updates), and its estimate agrees with the cell-count run within their statistical errors."""
+    import math
+    p = W.config2(N=1e4).with_(seed=21)
+    print("[gpu] measured cost model", flush=True)
+    ctx = dk.Context(0)
+    cells = dk.estimate(p, 1e-2, ctx=ctx)
+    meas = dk.estimate(p, 1e-2, ctx=ctx, cost_model=1)
+    ctx.close()
+    c = meas["cost"]
+    assert all(0 < x < 1.0 for x in c), c                       # seconds per sample
+    assert all(c[l] > c[l - 1] for l in range(1, len(c))), c    # (small levels carry launch latency)
+    assert c[-1] / c[0] > 100, c
+    se = math.sqrt(cells["var_est"][0] + meas["var_est"][0])
+    assert abs(cells["estimate"][0] - meas["estimate"][0]) < 4.5 * se
