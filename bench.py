@@ -40,7 +40,7 @@ VALU_PEAK_OPS = 256 * 128 * 2.4e9
 # size), scaled by what the counters read for a 256 MiB copy (fetch x2.0, write x1.0): a constant
 # per dispatch (the level tables, missed once per XCD) plus bytes per pair (the outputs).  It is
 # reported only while the kernel sources hash to the value the counters were taken on.
-TRAFFIC = {"sha256": "f2e4ee90aec607d2afd1ee4f3623dab1c34fa32b87c5f80b52820443bbb2577e",
+TRAFFIC = {"sha256": "34d2cca85b8f645fa881761bdd25ef4871457fe008e3f10417e627d045fda7bb",
            "fetch_bytes_per_dispatch": 1730.0 * 1024 * 2.0, "write_bytes_per_pair": 32.0 * 1.0,
            "profile": "profiles/level_kernel_128_pair_hbm_counters.md"}
 KERNEL_SOURCES = ["dk_level.h", "dk_rng.h", "dk_kernels.hip", "dk_internal.h"]
@@ -478,9 +478,11 @@ def bench_config4(args):
 
 def bench_config5(args):
     """Throughput scale (config 5): finest grids 256^2, 512^2 and 1024^2 (levels 4..6 of h = 1/16 ..
-    1/1024, N = 1e6, T = 26 tau_0), coupled pairs on the streaming kernel (state in HBM, 4 fine
-    steps per launch); args.samples pairs at 1024^2 and correspondingly more at the smaller grids.
-    Also the noise-free FP32 stencil, which is bound by HBM bandwidth."""
+    1/1024, N = 1e6, T = 26 tau_0), coupled pairs on the streaming kernel (state in HBM, depth
+    chosen by the tuner); args.samples pairs at 1024^2 and correspondingly more at the smaller
+    grids.  Then every temporal depth (1, 2, 4, 8 fine steps per launch) at 1024^2, pairs and
+    single paths, with the algorithmic HBM rate.  Also the noise-free FP32 stencil, which is
+    bound by HBM bandwidth."""
     import torch
     import dk_workloads as W
     import paper_2311_08872_amd as dk
@@ -504,6 +506,35 @@ def bench_config5(args):
                             "algorithmic_GB_per_s": 5.0 * cells / (st["kernel_ms"] / 1e3) / 1e9}
         print(f"[bench] config5 {p.n(l)}^2: {out[str(p.n(l))]['cell_updates_per_s']:.3g} cell updates/s",
               file=sys.stderr, flush=True)
+    # temporal depth: 128 pairs (and 128 single paths) at 1024^2 over 4096 fine steps per depth.
+    # Algorithmic HBM bytes per fine cell update (halo re-reads excluded): single paths 16/D (FP32
+    # value and compensation, read and written once per launch); pairs add the coarse state and,
+    # at D != 4, the restricted-noise sums that go through HBM: per 4 fine steps D = 1: 64 + 14 + 6,
+    # D = 2: 32 + 6 + 6, D = 4: 16 + 4; per 8 fine steps D = 8: 16 + 4 + 12.
+    pair_bytes = {1: 84 / 4, 2: 44 / 4, 4: 20 / 4, 8: 32 / 8}
+    ps = p.with_(T=p.tau(6) * 4096, steps_policy=W.STEPS_EXACT)
+    assert ps.steps(6) == 4096
+    depths = {}
+    for coupled in (True, False):
+        for d in (1, 2, 4, 8):
+            ctx.set_stream_depth(d)
+            ctx.reset()
+            if coupled:
+                dk.level_pair(ps, 6, 0, 128, ctx=ctx)
+            else:
+                dk.mc_level(ps, 6, 0, 128, ctx=ctx)
+            torch.cuda.synchronize()
+            st = [s for s in ctx.stats() if s["level"] == 6][0]
+            assert st["rows"] == -d
+            fine = st["cell_updates"] / (1 + 1 / 16 if coupled else 1.0)
+            rate = st["cell_updates"] / (st["kernel_ms"] / 1e3)
+            by = (pair_bytes[d] if coupled else 16.0 / d) * fine / (st["kernel_ms"] / 1e3)
+            depths[f"{'pair' if coupled else 'single'}_D{d}"] = {
+                "cell_updates_per_s": rate, "algorithmic_bytes_per_fine_update": pair_bytes[d] if coupled else 16.0 / d,
+                "algorithmic_GB_per_s": by / 1e9, "frac_of_8TBps": by / 8e12, "kernel_ms": st["kernel_ms"]}
+            print(f"[bench] config5 1024^2 {'pair' if coupled else 'single'} depth {d}: {rate:.3g} cell updates/s, "
+                  f"{by / 1e9:.0f} GB/s algorithmic ({100 * by / 8e12:.1f} % of 8 TB/s)", file=sys.stderr, flush=True)
+    ctx.set_stream_depth(0)
     heat = {}
     for n, batch in ((256, 4096), (1024, 256)):
         x = torch.ones((batch, n, n), dtype=torch.float32, device="cuda")
@@ -516,7 +547,7 @@ def bench_config5(args):
     fin = out[f"{p.n(6)}"]
     _report(f"config-5 throughput: coupled pairs at 256^2, 512^2, 1024^2 (N={N:g}, tau=0.1h^2, "
             f"{args.samples} pairs at 1024^2), streaming kernel", fin["cell_updates_per_s"], "cell updates/s",
-            {"grids": out, "noise_free_stencil": heat})
+            {"grids": out, "depths_1024": depths, "noise_free_stencil": heat})
 
 if __name__ == "__main__":
     main()

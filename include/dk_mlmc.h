@@ -316,7 +316,8 @@ typedef struct {
     uint64_t samples;         /* samples (or pairs) computed                 */
     double kernel_ms;         /* summed event time of the launches           */
     double cell_updates;      /* fine + coarse cell updates                  */
-    int32_t rows;             /* rows per lane of the tile shape used         */
+    int32_t rows;             /* rows per lane of the tile shape used; -D for  */
+                              /* the streaming kernel at temporal depth D      */
     int32_t reserved;
 } dk_kernel_stats;
 
@@ -334,25 +335,37 @@ int dk_context_reset(dk_context* ctx, int32_t drop_tables);
 int dk_context_set_shape(dk_context* ctx, int32_t n, int32_t variant);
 int dk_shape_rows(int32_t n, int32_t variant);
 
-/* The autotuner's tile-shape choices of the context (and those loaded) as JSON text:
+/* The autotuner's tile-shape and streaming-depth choices of the context (and those loaded) as
+ * JSON text:
  *   {"format": "dk-tile-shapes-1", "arch": "gfx950",
- *    "shapes": [{"n": 128, "pair": 1, "flux": 0, "rows": 8}, ...]}
+ *    "shapes": [{"n": 128, "pair": 1, "flux": 0, "rows": 8}, {"n": 1024, "pair": 1, "flux": 0,
+ *               "depth": 4}, ...]}
  * Writes at most cap bytes including the terminating NUL into buf (buf may be NULL when cap is
  * 0) and returns the text's full length without the NUL, or a negative error code. */
 int dk_context_tuning_json(dk_context* ctx, char* buf, uint64_t cap);
 /* Loads choices in that format; listed shapes replace the context's choices and are used
- * without timing.  DK_EINVAL if the text lacks the format tag, names another architecture or
- * lists a row count that no compiled shape of that grid has.  With the environment variable
- * DK_TUNE_CACHE set to a file path, every context loads that file when it is created (if it
- * exists and is valid) and rewrites it whenever the autotuner makes a new choice. */
+ * without timing.  DK_EINVAL if the text lacks the format tag, names another architecture,
+ * lists a row count that no compiled shape of that grid has, or a depth other than 1, 2, 4, 8.
+ * With the environment variable DK_TUNE_CACHE set to a file path, every context loads that file
+ * when it is created (if it exists and is valid) and rewrites it whenever the autotuner makes a
+ * new choice. */
 int dk_context_load_tuning_json(dk_context* ctx, const char* json);
 
 /* Grids larger than 128 x 128 (multiples of 64) run on the streaming kernel: the FP32 state
- * stays in HBM (double-buffered), each launch advances 64 x 64 tiles with a 4-cell halo by 4
- * fine steps (one coarse step for pairs), regenerating the halo's noise.  Its fields are
- * bit-identical to the resident kernel's.  dk_context_set_streaming(ctx, 1) routes every level
- * of size >= 64 through it (for comparison); field output is not available there. */
+ * stays in HBM (double-buffered), each launch advances 64 x 64 tiles with a halo of max(D, 2)
+ * cells by D fine steps (temporal depth D in {1, 2, 4, 8}), regenerating the halo's noise.  For
+ * pairs the coarse step (Sec. 4, one per 4 fine steps) is fused into the launch at D = 4; at the
+ * other depths the restricted-noise sums go through HBM and a coarse kernel takes the step.  Its
+ * fields are bit-identical to the resident kernel's at every depth.  dk_context_set_streaming(ctx,
+ * 1) routes every level of size >= 64 through it (for comparison); field output is not
+ * available there. */
 int dk_context_set_streaming(dk_context* ctx, int32_t on);
+/* Temporal depth of the streaming kernel: 1, 2, 4 or 8 forces it for every streamed level; 0
+ * (the default) times the four depths on a short batch (16 fine steps, up to 64 samples) the
+ * first time a job of >= 1e11 cell updates runs a grid size, keeps the fastest (listed in the
+ * tuning JSON as {"n": .., "pair": .., "flux": .., "depth": D}) and uses depth 4 for smaller
+ * jobs.  DK_EINVAL for other values.  The depth changes no result. */
+int dk_context_set_stream_depth(dk_context* ctx, int32_t depth);
 
 /* Largest work of one sampling launch, in fine + coarse cell updates (default 2e12, about 5 s
  * on MI355X; 0 restores the default, values below 1e6 are raised to 1e6).  Longer levels are

@@ -135,7 +135,7 @@ class Context:
         _check(self.lib.dk_context_set_shape(self.h, n, variant))
 
     def tuning_json(self) -> str:
-        """The autotuner's tile-shape choices as JSON text."""
+        """The autotuner's tile-shape and streaming-depth choices as JSON text."""
         n = _check(self.lib.dk_context_tuning_json(self.h, None, 0))
         buf = C.create_string_buffer(n + 1)
         _check(self.lib.dk_context_tuning_json(self.h, buf, n + 1))
@@ -152,6 +152,10 @@ class Context:
     def set_streaming(self, on: bool):
         """Route levels of size >= 64 through the HBM-streaming kernel (comparison / testing)."""
         _check(self.lib.dk_context_set_streaming(self.h, int(on)))
+
+    def set_stream_depth(self, depth: int):
+        """Temporal depth of the streaming kernel: 1, 2, 4 or 8 fine steps per launch (0: automatic)."""
+        _check(self.lib.dk_context_set_stream_depth(self.h, int(depth)))
 
     @staticmethod
     def shape_rows(n: int, variant: int) -> int:

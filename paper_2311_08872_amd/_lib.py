@@ -99,6 +99,7 @@ SIGNATURES = {
     "dk_context_tuning_json": (C.c_int, [C.c_void_p, C.c_char_p, C.c_uint64]),
     "dk_context_load_tuning_json": (C.c_int, [C.c_void_p, C.c_char_p]),
     "dk_context_set_streaming": (C.c_int, [C.c_void_p, C.c_int32]),
+    "dk_context_set_stream_depth": (C.c_int, [C.c_void_p, C.c_int32]),
     "dk_heat_steps": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_void_p, C.c_void_p,
                                 C.POINTER(C.c_double), C.c_void_p]),
     "dk_last_error": (C.c_char_p, []),

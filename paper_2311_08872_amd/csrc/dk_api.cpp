@@ -17,6 +17,8 @@
 
 #include "dk_cnn.h"
 #include "dk_internal.h"
+#include "dk_round.h"
+#include "dk_stream.h"
 #include <fstream>
 #include <random>
 #include <regex>
@@ -209,6 +211,8 @@ struct dk_context {
     std::map<std::pair<int, int>, KStat> stats;
     std::map<int, int> forced_shape;          // grid size -> tile-shape variant
     bool force_stream = false;                // run every level with the streaming kernel
+    int stream_depth = 0;                     // forced temporal depth of the streaming kernel (0: automatic)
+    std::map<long, int> tuned_depth;          // (nf, pair, flux) -> streaming depth chosen by timing
     double max_launch_cells = kMaxCellsPerLaunch;   // work cap of one sampling launch
     // concurrent rounds: one stream per level, fork/join events, per-level buffers
     hipStream_t lvl_stream[DK_MAX_LEVELS] = {};
@@ -236,6 +240,7 @@ struct dk_context {
     DevBuf mf0, mf1;       // mean-field streaming buffers
     DevBuf scratch_c;      // inner products
     DevBuf st_f[2][2], st_c[2][2];   // streaming state: [buffer][rho, cmp] fine / coarse
+    DevBuf st_z;                     // streaming pairs: restricted-noise sums of split depths
     std::vector<double> host_mom;
     // learned control variate
     dk::cnn::Workspace cnn;
@@ -393,6 +398,12 @@ std::string tuning_json(const dk_context* ctx)
           << ", \"rows\": " << dk::shape_rows(nf, kv.second) << "}";
         first = false;
     }
+    for (const auto& kv : ctx->tuned_depth) {
+        const int nf = (int)(kv.first >> 8), pair = (int)((kv.first >> 4) & 0xF), flux = (int)(kv.first & 0xF);
+        o << (first ? "" : ", ") << "{\"n\": " << nf << ", \"pair\": " << pair << ", \"flux\": " << flux
+          << ", \"depth\": " << kv.second << "}";
+        first = false;
+    }
     o << "]}";
     return o.str();
 }
@@ -408,7 +419,17 @@ int load_tuning_json(dk_context* ctx, const std::string& text)
     if (!std::regex_search(text, m, arch)) return fail(DK_EINVAL, "tuning JSON: missing \"arch\"");
     const std::string dev = device_arch(ctx->device);
     if (m[1].str() != dev) return fail(DK_EINVAL, "tuning JSON is for %s, the device is %s", m[1].str().c_str(), dev.c_str());
-    std::map<long, int> got;
+    static const std::regex dentry("\\{\\s*\"n\"\\s*:\\s*(\\d+)\\s*,\\s*\"pair\"\\s*:\\s*(\\d+)\\s*,\\s*\"flux\"\\s*:\\s*(\\d+)"
+                                   "\\s*,\\s*\"depth\"\\s*:\\s*(\\d+)\\s*\\}");
+    std::map<long, int> got, gotd;
+    for (auto it = std::sregex_iterator(text.begin(), text.end(), dentry); it != std::sregex_iterator(); ++it) {
+        const int nf = std::stoi((*it)[1]), pair = std::stoi((*it)[2]), flux = std::stoi((*it)[3]);
+        const int depth = std::stoi((*it)[4]);
+        if (pair > 1 || (flux != DK_FLUX_CENTRAL && flux != DK_FLUX_STAGGERED) || !dk::stream_supported(nf) ||
+            !dk::stream_depth_supported(depth))
+            return fail(DK_EINVAL, "tuning JSON: bad streaming entry for n = %d", nf);
+        gotd[((long)nf << 8) | ((long)pair << 4) | (long)flux] = depth;
+    }
     for (auto it = std::sregex_iterator(text.begin(), text.end(), entry); it != std::sregex_iterator(); ++it) {
         const int nf = std::stoi((*it)[1]), pair = std::stoi((*it)[2]), flux = std::stoi((*it)[3]);
         const int rows = std::stoi((*it)[4]);
@@ -420,6 +441,7 @@ int load_tuning_json(dk_context* ctx, const std::string& text)
         got[((long)nf << 8) | ((long)pair << 4) | (long)flux] = v;
     }
     for (const auto& kv : got) ctx->tuned[kv.first] = kv.second;
+    for (const auto& kv : gotd) ctx->tuned_depth[kv.first] = kv.second;
     return DK_OK;
 }
 
@@ -500,8 +522,52 @@ int choose_shape(dk_context* ctx, const dk_problem* p, bool pair, const dk::Leve
     return DK_OK;
 }
 
-// Grids beyond the resident kernel: state in HBM, batches of samples, one launch per coarse step
-// (4 fine steps; single-level runs end with a shorter launch), then the observables.
+// Grids beyond the resident kernel: state in HBM, batches of samples, launches of `depth` fine
+// steps (the last one shorter if the step count is not a multiple), coarse steps fused into the
+// depth-4 launches or taken by the coarse kernel after each group of 4, then the observables.
+// The depth is forced (dk_context_set_stream_depth), cached, or chosen by timing the four depths
+// on a short batch the first time a large job runs a grid size.
+int stream_pass(dk_context* ctx, const dk_problem* p, bool pair, int depth, const dk::LevelArgs& A, uint64_t first,
+                int c, int steps, size_t zgroup, hipStream_t s, int* cur_f, int* cur_c)
+{
+    const int nf = A.nf, nc = nf / 2;
+    HIP_TRY(dk::launch_stream_init((const float*)A.rho0_f, nf, c, (float*)ctx->st_f[0][0].p, (float*)ctx->st_f[0][1].p, s));
+    if (pair)
+        HIP_TRY(dk::launch_stream_init((const float*)A.rho0_c, nc, c, (float*)ctx->st_c[0][0].p, (float*)ctx->st_c[0][1].p, s));
+    dk::StreamArgs S{};
+    S.n = nf; S.level_id = A.level_id; S.tag = A.tag; S.seed = A.seed; S.first = first; S.count = c;
+    S.a = (float)A.a; S.kf = (float)A.kf; S.kc = (float)A.kc;
+    S.z = pair && depth != 4 ? (float*)ctx->st_z.p : nullptr;
+    S.zgroup = zgroup;
+    int cf = 0, cc = 0;
+    for (int m0 = 0; m0 < steps; m0 += depth) {
+        S.m0 = m0;
+        S.ksteps = std::min(depth, steps - m0);
+        S.do_coarse = pair && depth == 4 ? 1 : 0;
+        S.z_load = pair && depth != 4 && m0 % 4 != 0 ? 1 : 0;
+        S.rho_in = (const float*)ctx->st_f[cf][0].p; S.cmp_in = (const float*)ctx->st_f[cf][1].p;
+        S.rho_out = (float*)ctx->st_f[1 - cf][0].p; S.cmp_out = (float*)ctx->st_f[1 - cf][1].p;
+        if (pair) {
+            S.rhoc_in = (const float*)ctx->st_c[cc][0].p; S.cmpc_in = (const float*)ctx->st_c[cc][1].p;
+            S.rhoc_out = (float*)ctx->st_c[1 - cc][0].p; S.cmpc_out = (float*)ctx->st_c[1 - cc][1].p;
+        }
+        HIP_TRY(dk::launch_stream_step(S, pair, p->flux, depth, s));
+        cf = 1 - cf;
+        if (!pair) continue;
+        if (depth == 4) { cc = 1 - cc; continue; }
+        const int groups = depth == 8 ? S.ksteps / 4 : ((m0 + S.ksteps) % 4 == 0 ? 1 : 0);
+        for (int g = 0; g < groups; ++g) {
+            HIP_TRY(dk::launch_stream_coarse(nc, c, S.a, S.kc, p->flux, (const float*)ctx->st_c[cc][0].p,
+                                             (const float*)ctx->st_c[cc][1].p, (const float*)ctx->st_z.p + 2 * g * zgroup,
+                                             (float*)ctx->st_c[1 - cc][0].p, (float*)ctx->st_c[1 - cc][1].p, s));
+            cc = 1 - cc;
+        }
+    }
+    *cur_f = cf;
+    *cur_c = cc;
+    return DK_OK;
+}
+
 int run_stream(dk_context* ctx, const dk_problem* p, int level, bool pair, uint64_t first, uint64_t count, uint32_t tag,
                const dk::LevelArgs& A, dk_moments* sums_out, double* per_sample_out, hipStream_t s,
                double* cell_updates, uint64_t nchunks_unused, uint64_t ch_unused, size_t mom_stride)
@@ -509,7 +575,8 @@ int run_stream(dk_context* ctx, const dk_problem* p, int level, bool pair, uint6
     const int nf = A.nf, nc = nf / 2;
     const int nobs = p->n_obs;
     const size_t nn = (size_t)nf * nf, ncc = (size_t)nc * nc;
-    const size_t per_sample_bytes = 2 * 2 * 4 * (nn + (pair ? ncc : 0));
+    // state [buffer][rho, cmp] fine and coarse, and two groups of restricted-noise sums
+    const size_t per_sample_bytes = 2 * 2 * 4 * (nn + (pair ? ncc : 0)) + (pair ? 2 * 8 * ncc : 0);
     uint64_t B = std::max<uint64_t>(1, (4ull << 30) / per_sample_bytes);
     B = std::min<uint64_t>({B, count, 4096ull});
     int rc;
@@ -518,6 +585,8 @@ int run_stream(dk_context* ctx, const dk_problem* p, int level, bool pair, uint6
             if ((rc = ctx->st_f[b][k].ensure(4 * nn * B))) return rc;
             if (pair && (rc = ctx->st_c[b][k].ensure(4 * ncc * B))) return rc;
         }
+    const size_t zgroup = ncc * B;
+    if (pair && (rc = ctx->st_z.ensure(2 * 8 * zgroup))) return rc;
     const uint64_t nbatch = (count + B - 1) / B;
     if (!per_sample_out && (rc = ctx->per_sample.ensure(sizeof(double) * 2 * nobs * B))) return rc;
     if ((rc = ctx->moments.ensure(sizeof(double) * mom_stride * nbatch))) return rc;
@@ -528,35 +597,54 @@ int run_stream(dk_context* ctx, const dk_problem* p, int level, bool pair, uint6
     }
     const bool log = std::getenv("DK_LOG") != nullptr;
     const int steps = A.steps;
+    const double cells_per_sample = (double)nn * (double)steps * (pair ? 1.0 + 1.0 / 16.0 : 1.0);
+    int depth = ctx->stream_depth;
+    if (depth == 0) {
+        const long key = ((long)nf << 8) | ((long)pair << 4) | (long)p->flux;
+        auto t = ctx->tuned_depth.find(key);
+        if (t != ctx->tuned_depth.end()) {
+            depth = t->second;
+        } else if ((double)count * cells_per_sample < 1e11) {
+            depth = 4;
+        } else {
+            // time each depth on 16 fine steps of a short batch (outputs discarded)
+            const int tc = (int)std::min<uint64_t>(B, 64);
+            const int ts = std::min(steps, 16);
+            hipEvent_t e0 = ctx->ev_pool[0], e1 = ctx->ev_pool[1];
+            double best = 1e300;
+            int cf, cc;
+            ctx->tune_log.clear();
+            for (int d : {1, 2, 4, 8}) {
+                if ((rc = stream_pass(ctx, p, pair, d, A, first, tc, ts, zgroup, s, &cf, &cc))) return rc;   // warm-up
+                HIP_TRY(hipEventRecord(e0, s));
+                if ((rc = stream_pass(ctx, p, pair, d, A, first, tc, ts, zgroup, s, &cf, &cc))) return rc;
+                HIP_TRY(hipEventRecord(e1, s));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                ctx->tune_log.push_back(std::make_pair(d, (double)ms));
+                if (ms < best) { best = ms; depth = d; }
+            }
+            ctx->tuned_depth[key] = depth;
+            save_tuning_cache(ctx);
+            if (log) {
+                std::fprintf(stderr, "[dk] tuned streaming depth n=%d pair=%d flux=%d:", nf, (int)pair, p->flux);
+                for (auto& kv : ctx->tune_log) std::fprintf(stderr, " D=%d %.3f ms", kv.first, kv.second);
+                std::fprintf(stderr, " -> D=%d\n", depth);
+                std::fflush(stderr);
+            }
+        }
+    }
     for (uint64_t bi = 0; bi < nbatch; ++bi) {
         const uint64_t b0 = bi * B;
         const int c = (int)std::min<uint64_t>(B, count - b0);
         double* out = per_sample_out ? per_sample_out + b0 * nobs * 2 : (double*)ctx->per_sample.p;
         HIP_TRY(hipEventRecord(ctx->ev_pool[2 * bi], s));
-        HIP_TRY(dk::launch_stream_init((const float*)A.rho0_f, nf, c, (float*)ctx->st_f[0][0].p, (float*)ctx->st_f[0][1].p, s));
-        if (pair)
-            HIP_TRY(dk::launch_stream_init((const float*)A.rho0_c, nc, c, (float*)ctx->st_c[0][0].p,
-                                           (float*)ctx->st_c[0][1].p, s));
-        dk::StreamArgs S{};
-        S.n = nf; S.level_id = A.level_id; S.tag = A.tag; S.seed = A.seed; S.first = first + b0; S.count = c;
-        S.a = (float)A.a; S.kf = (float)A.kf; S.kc = (float)A.kc;
-        int cur = 0;
-        for (int m0 = 0; m0 < steps; m0 += 4) {
-            S.m0 = m0;
-            S.ksteps = std::min(4, steps - m0);
-            S.do_coarse = pair ? 1 : 0;
-            S.rho_in = (const float*)ctx->st_f[cur][0].p; S.cmp_in = (const float*)ctx->st_f[cur][1].p;
-            S.rho_out = (float*)ctx->st_f[1 - cur][0].p; S.cmp_out = (float*)ctx->st_f[1 - cur][1].p;
-            if (pair) {
-                S.rhoc_in = (const float*)ctx->st_c[cur][0].p; S.cmpc_in = (const float*)ctx->st_c[cur][1].p;
-                S.rhoc_out = (float*)ctx->st_c[1 - cur][0].p; S.cmpc_out = (float*)ctx->st_c[1 - cur][1].p;
-            }
-            HIP_TRY(dk::launch_stream_step(S, pair, p->flux, s));
-            cur = 1 - cur;
-        }
+        int cur = 0, curc = 0;
+        if ((rc = stream_pass(ctx, p, pair, depth, A, first + b0, c, steps, zgroup, s, &cur, &curc))) return rc;
         HIP_TRY(dk::launch_stream_observe((const float*)ctx->st_f[cur][0].p, nf, c, A.phi_f, A.obs_f, nobs, A.h2f, out, 0, s));
         if (pair)
-            HIP_TRY(dk::launch_stream_observe((const float*)ctx->st_c[cur][0].p, nc, c, A.phi_c, A.obs_c, nobs, A.h2c, out, 1, s));
+            HIP_TRY(dk::launch_stream_observe((const float*)ctx->st_c[curc][0].p, nc, c, A.phi_c, A.obs_c, nobs, A.h2c, out, 1, s));
         else
             HIP_TRY(dk::launch_zero_slot(out, c, nobs, 1, s));
         HIP_TRY(hipEventRecord(ctx->ev_pool[2 * bi + 1], s));
@@ -572,7 +660,6 @@ int run_stream(dk_context* ctx, const dk_problem* p, int level, bool pair, uint6
     HIP_TRY(hipMemcpyAsync(ctx->host_mom.data(), ctx->moments.p, sizeof(double) * mom_stride * nbatch,
                            hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    const double cells_per_sample = (double)nn * (double)steps * (pair ? 1.0 + 1.0 / 16.0 : 1.0);
     {
         KStat& st = ctx->stats[std::make_pair(level, pair ? 1 : 0)];
         for (uint64_t k = 0; k < nbatch; ++k) {
@@ -583,7 +670,7 @@ int run_stream(dk_context* ctx, const dk_problem* p, int level, bool pair, uint6
         st.launches += nbatch;
         st.samples += count;
         st.cells += cells_per_sample * (double)count;
-        st.rows = -1;   // streamed
+        st.rows = -depth;   // streamed, temporal depth |rows|
     }
     for (uint64_t k = 0; k < nbatch; ++k) {
         const uint64_t c = std::min(B, count - k * B);
@@ -1834,6 +1921,7 @@ int dk_context_reset(dk_context* ctx, int32_t drop_tables)
     if (drop_tables) {
         ctx->problems.clear();
         ctx->tuned.clear();
+        ctx->tuned_depth.clear();
     }
     return DK_OK;
 }
@@ -1890,6 +1978,15 @@ int dk_context_set_streaming(dk_context* ctx, int32_t on)
 {
     if (!ctx) return fail(DK_EINVAL, "context is NULL");
     ctx->force_stream = on != 0;
+    return DK_OK;
+}
+
+int dk_context_set_stream_depth(dk_context* ctx, int32_t depth)
+{
+    if (!ctx) return fail(DK_EINVAL, "context is NULL");
+    if (depth != 0 && !dk::stream_depth_supported(depth))
+        return fail(DK_EINVAL, "streaming depth %d: use 1, 2, 4, 8 or 0 (automatic)", depth);
+    ctx->stream_depth = depth;
     return DK_OK;
 }
 

@@ -14,7 +14,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "dk_internal.h"
+#include "dk_round.h"
 #include "dk_level.h"
 
 namespace dk {

@@ -1,49 +1,66 @@
 // dk_stream.hip -- the level kernel for grids that do not fit on chip (n >= 256; any multiple
-// of 64 works), with the state in HBM and 4-step temporal blocking.
+// of 64 works), with the state in HBM and temporal blocking of depth D in {1, 2, 4, 8}.
 //
-// One launch advances a batch of samples by up to 4 fine steps -- for coupled pairs exactly the
-// 4 fine steps of one coarse step, followed by that coarse step.  Each block owns a 64 x 64 fine
-// tile of one sample and loads it with a 4-cell halo (72 x 72) into LDS.  The noise of the halo
-// is regenerated from the counter-based generator (it is a pure function of site and step), so
-// no noise is exchanged; the valid region shrinks by one cell per step.  The state is
-// double-buffered in HBM (read buffer / write buffer alternate by launch), so neighbouring tiles
-// never read cells another block is writing.
+// One launch advances a batch of samples by up to D fine steps.  Each block owns a 64 x 64 fine
+// tile of one sample and loads it with a halo of H = max(D, 2) cells into LDS (H is even so that
+// the 2 x 2 blocks below line up with the coarse cells and with the horizontal site pairs that
+// share a generator call).  The noise of the halo is regenerated from the counter-based
+// generator (it is a pure function of site and step), so no noise is exchanged; the valid
+// region shrinks by one cell per step.  The state is double-buffered in HBM (read buffer / write
+// buffer alternate by launch), so neighbouring tiles never read cells another block is writing.
+//
+// Coupled pairs: the coarse grid takes one step per 4 fine steps with the restricted noise, the
+// sum of the fine noise over the coarse cell's 2 x 2 fine sites and those 4 steps.  At D = 4 a
+// launch covers exactly one coarse step and takes it at its end, in the same kernel (the coarse
+// halo's sums come from the fine halo).  At the other depths each block keeps the sums of its
+// own coarse cells in an HBM buffer (loaded when a launch continues a group of 4 steps, stored
+// at its end; D = 8 stores two groups) and a separate coarse kernel takes the coarse step once
+// a group is complete.
 //
 // The per-cell arithmetic (explicit FMAs, Kahan-compensated increment, coarse-noise sums added
 // as (even-row block sum + odd-row block sum)) is the same operation sequence as the resident
-// kernel, so both produce bit-identical fields.
+// kernel, so every depth produces bit-identical fields.
 //
-// Lane work: a block of 512 threads owns the 36 x 36 = 1296 2x2 blocks of the extended tile
-// (thread t owns blocks t, t + 512, t + 1024); each 2x2 block is two Philox calls per step (one per
+// Lane work: a block of 512 threads (640 at D = 8) owns the (32 + H)^2 2x2 blocks of the extended
+// tile, three per thread (thread t owns blocks t, t + 512, t + 1024); each 2x2 block is two generator calls per step (one per
 // horizontal site pair) and holds its cells' compensation terms and its coarse cell's noise sum
 // in registers.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "dk_internal.h"
+#include "dk_stream.h"
 #include "dk_rng.h"
 
 namespace dk {
 
 namespace {
 constexpr int TT = 64;               // fine tile interior
-constexpr int HH = 4;                // halo = fine steps per launch
-constexpr int EXT = TT + 2 * HH;     // 72
-constexpr int NBS = EXT / 2;         // 36 blocks per side
-constexpr int NBLK = NBS * NBS;      // 1296
-constexpr int THREADS = 512;
-constexpr int BPT = (NBLK + THREADS - 1) / THREADS;   // 3
 constexpr int CT = TT / 2;           // coarse tile interior (32)
-constexpr int CEXT = CT + 2;         // coarse tile with a 1-cell halo (34)
+constexpr int CEXT = CT + 2;         // coarse tile with a 1-cell halo (34), fused coarse step
+
+template <int D>
+struct Geo {
+    static constexpr int THREADS = D == 8 ? 640 : 512;        // 3 blocks per thread at every depth
+    static constexpr int HH = D < 2 ? 2 : D;                  // halo width
+    static constexpr int EXT = TT + 2 * HH;                   // extended tile side
+    static constexpr int NBS = EXT / 2;                       // 2x2 blocks per side
+    static constexpr int NBLK = NBS * NBS;
+    static constexpr int BPT = (NBLK + THREADS - 1) / THREADS;
+};
 
 __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 __device__ __forceinline__ float psq(float x) { return __builtin_amdgcn_sqrtf(__builtin_fmaxf(x, 0.0f)); }
 }  // namespace
 
-template <int FLUX, bool PAIR>
-__global__ void __launch_bounds__(THREADS, 4) stream_kernel(const StreamArgs A)
+template <int FLUX, bool PAIR, int D>
+__global__ void __launch_bounds__(Geo<D>::THREADS, 4) stream_kernel(const StreamArgs A)
 {
 #pragma clang fp contract(off)
+    constexpr int THREADS = Geo<D>::THREADS;
+    constexpr int HH = Geo<D>::HH, EXT = Geo<D>::EXT, NBS = Geo<D>::NBS, NBLK = Geo<D>::NBLK, BPT = Geo<D>::BPT;
+    constexpr bool FUSED = PAIR && D == 4;     // coarse step taken by this kernel
+    constexpr bool SPLIT = PAIR && D != 4;     // noise sums kept in HBM, coarse step by its own kernel
+    constexpr int HB = HH / 2;                 // first block of the tile interior
     __shared__ float sr[EXT * EXT];
     __shared__ float sf0[EXT * EXT];
     __shared__ float sf1[EXT * EXT];
@@ -52,6 +69,8 @@ __global__ void __launch_bounds__(THREADS, 4) stream_kernel(const StreamArgs A)
     const int tile = blockIdx.x;
     const int sidx = blockIdx.y;
     const int tx0 = (tile % tiles_x) * TT, ty0 = (tile / tiles_x) * TT;
+    const int cx0 = tx0 / 2, cy0 = ty0 / 2;
+    const int nc = n / 2;
     const uint64_t sample = A.first + sidx;
     const size_t nn = (size_t)n * n;
     const float* rin = A.rho_in + sidx * nn;
@@ -61,9 +80,14 @@ __global__ void __launch_bounds__(THREADS, 4) stream_kernel(const StreamArgs A)
     const int t = threadIdx.x;
     const NoiseKey key = make_key(A.seed, A.tag, A.level_id, sample);
     const uint32_t ppr = (uint32_t)(n / 2);
+    // (split pairs) block (bx, by) of the interior <-> coarse cell (cx0 + bx - HB, cy0 + by - HB)
+    auto zslot = [&](int bx, int by, int group) -> float2* {
+        return (float2*)A.z + group * A.zgroup + ((size_t)sidx * nc + (cy0 + by - HB)) * nc + (cx0 + bx - HB);
+    };
+    auto interior = [&](int bx, int by) { return bx >= HB && bx < HB + CT && by >= HB && by < HB + CT; };
 
     float cmp[BPT][4], Z[BPT][2];
-    // load the extended tile
+    // load the extended tile (and, continuing a group, the running noise sums)
 #pragma unroll
     for (int k = 0; k < BPT; ++k) {
         const int b = t + k * THREADS;
@@ -78,6 +102,13 @@ __global__ void __launch_bounds__(THREADS, 4) stream_kernel(const StreamArgs A)
                 sr[ey * EXT + ex] = rin[(size_t)gy * n + gx];
                 cmp[k][q] = cin[(size_t)gy * n + gx];
             }
+            if constexpr (SPLIT) {
+                if (A.z_load && interior(bx, by)) {
+                    const float2 zz = *zslot(bx, by, 0);
+                    Z[k][0] = zz.x;
+                    Z[k][1] = zz.y;
+                }
+            }
         }
     }
     __syncthreads();
@@ -85,9 +116,9 @@ __global__ void __launch_bounds__(THREADS, 4) stream_kernel(const StreamArgs A)
     const float a = A.a, kappa = A.kf;
     for (int j = 0; j < A.ksteps; ++j) {
         const uint32_t m = (uint32_t)(A.m0 + j);
-        // noise is needed on the flux region [j, EXT - j) and, for pairs, on the blocks whose
-        // coarse cell is in the coarse tile plus its halo (ext [2, EXT - 2))
-        const int lo = PAIR ? (j < 2 ? j : 2) : j;
+        // noise is needed on the flux region [j, EXT - j) and, for the fused coarse step, on the
+        // blocks whose coarse cell is in the coarse tile plus its halo (ext [2, EXT - 2))
+        const int lo = FUSED ? (j < 2 ? j : 2) : j;
         const int hi = EXT - lo;
 #pragma unroll
         for (int k = 0; k < BPT; ++k) {
@@ -105,11 +136,14 @@ __global__ void __launch_bounds__(THREADS, 4) stream_kernel(const StreamArgs A)
                 site_pair_normals(key, idx, m, a0, a1, b0, b1);
                 w0[2 * r] = a0; w1[2 * r] = a1; w0[2 * r + 1] = b0; w1[2 * r + 1] = b1;
             }
-            if constexpr (PAIR) {
+            if constexpr (FUSED) {
                 if (bx >= 1 && bx < NBS - 1 && by >= 1 && by < NBS - 1) {
                     Z[k][0] += (w0[0] + w0[1]) + (w0[2] + w0[3]);
                     Z[k][1] += (w1[0] + w1[1]) + (w1[2] + w1[3]);
                 }
+            } else if constexpr (SPLIT) {
+                Z[k][0] += (w0[0] + w0[1]) + (w0[2] + w0[3]);
+                Z[k][1] += (w1[0] + w1[1]) + (w1[2] + w1[3]);
             }
             // fluxes of all 4 cells: those outside this step's region get values no valid update reads
 #pragma unroll
@@ -126,6 +160,19 @@ __global__ void __launch_bounds__(THREADS, 4) stream_kernel(const StreamArgs A)
                     const float ry = sr[ey + 1 < EXT ? c + EXT : c];
                     sf0[c] = psq(0.5f * (rv + rx)) * w0[q];
                     sf1[c] = psq(0.5f * (rv + ry)) * w1[q];
+                }
+            }
+        }
+        if constexpr (SPLIT) {
+            // a group of 4 fine steps is complete (D = 8: two per launch), or the launch ends
+            if ((D == 8 && j == 3) || j == A.ksteps - 1) {
+#pragma unroll
+                for (int k = 0; k < BPT; ++k) {
+                    const int b = t + k * THREADS;
+                    const int bx = b % NBS, by = b / NBS;
+                    if (b < NBLK && interior(bx, by)) *zslot(bx, by, D == 8 ? (j >> 2) : 0) = make_float2(Z[k][0], Z[k][1]);
+                    Z[k][0] = 0.f;
+                    Z[k][1] = 0.f;
                 }
             }
         }
@@ -186,16 +233,14 @@ __global__ void __launch_bounds__(THREADS, 4) stream_kernel(const StreamArgs A)
             cout[g] = cmp[k][q];
         }
     }
-    if constexpr (PAIR) {
+    if constexpr (FUSED) {
         if (!A.do_coarse) return;
         // one coarse EM step with the restricted noise Z (coarse tile + 1 halo cell), reusing LDS
-        const int nc = n / 2;
         const size_t ncc = (size_t)nc * nc;
         const float* rcin = A.rhoc_in + sidx * ncc;
         const float* ccin = A.cmpc_in + sidx * ncc;
         float* rcout = A.rhoc_out + sidx * ncc;
         float* ccout = A.cmpc_out + sidx * ncc;
-        const int cx0 = tx0 / 2, cy0 = ty0 / 2;
         __syncthreads();
         float* scr = sr;                 // [CEXT][CEXT]
         float* scf0 = sf0;
@@ -245,6 +290,45 @@ __global__ void __launch_bounds__(THREADS, 4) stream_kernel(const StreamArgs A)
             ccout[g] = (tv - rv) - y;
         }
     }
+}
+
+// One coarse EM step of a batch of coarse grids from completed restricted-noise sums z
+// ([count][nc][nc] pairs, as stored by the split-depth pair kernels): a thread per coarse cell,
+// the operation sequence of the fused coarse step, so both give bit-identical coarse fields.
+template <int FLUX>
+__global__ void __launch_bounds__(256) stream_coarse_kernel(const int nc, const size_t total, const float a,
+                                                            const float kc, const float* __restrict__ rin,
+                                                            const float* __restrict__ cin,
+                                                            const float2* __restrict__ z, float* __restrict__ rout,
+                                                            float* __restrict__ cout)
+{
+#pragma clang fp contract(off)
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const size_t ncc = (size_t)nc * nc;
+    const size_t base = i - i % ncc;
+    const int c = (int)(i % ncc);
+    const int x = c % nc, y = c / nc;
+    const int xm = x == 0 ? nc - 1 : x - 1, xp = x == nc - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? nc - 1 : y - 1, yp = y == nc - 1 ? 0 : y + 1;
+    const float* r = rin + base;
+    const float2* zz = z + base;
+    const int cl = y * nc + xm, cr = y * nc + xp, cu = ym * nc + x, cd = yp * nc + x;
+    const float rv = r[c], rl = r[cl], rr = r[cr], ru = r[cu], rd = r[cd];
+    const float lap = fmaf(-4.0f, rv, (rl + rr) + (ru + rd));
+    float div;
+    if (FLUX == DK_FLUX_CENTRAL) {
+        div = (psq(rr) * zz[cr].x - psq(rl) * zz[cl].x) + (psq(rd) * zz[cd].y - psq(ru) * zz[cu].y);
+    } else {
+        const float f0 = psq(0.5f * (rv + rr)) * zz[c].x, f0m = psq(0.5f * (rl + rv)) * zz[cl].x;
+        const float f1 = psq(0.5f * (rv + rd)) * zz[c].y, f1m = psq(0.5f * (ru + rv)) * zz[cu].y;
+        div = (f0 - f0m) + (f1 - f1m);
+    }
+    const float d = fmaf(kc, div, a * lap);
+    const float y2 = d - cin[i];
+    const float tv = rv + y2;
+    rout[i] = tv;
+    cout[i] = (tv - rv) - y2;
 }
 
 // state initialisation: rho = rho0 table, compensation 0
@@ -353,16 +437,44 @@ hipError_t launch_heat_f32(const float* in, float* out, int n, int batch, float 
 
 bool stream_supported(int nf) { return nf >= 64 && nf % TT == 0; }
 
-hipError_t launch_stream_step(const StreamArgs& A, bool pair, int flux, hipStream_t s)
+template <int FLUX, bool PAIR>
+static hipError_t launch_depth(const StreamArgs& A, int depth, dim3 grid, hipStream_t s)
 {
+    switch (depth) {
+    case 1: hipLaunchKernelGGL((stream_kernel<FLUX, PAIR, 1>), grid, dim3(Geo<1>::THREADS), 0, s, A); break;
+    case 2: hipLaunchKernelGGL((stream_kernel<FLUX, PAIR, 2>), grid, dim3(Geo<2>::THREADS), 0, s, A); break;
+    case 4: hipLaunchKernelGGL((stream_kernel<FLUX, PAIR, 4>), grid, dim3(Geo<4>::THREADS), 0, s, A); break;
+    case 8: hipLaunchKernelGGL((stream_kernel<FLUX, PAIR, 8>), grid, dim3(Geo<8>::THREADS), 0, s, A); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+bool stream_depth_supported(int depth) { return depth == 1 || depth == 2 || depth == 4 || depth == 8; }
+
+hipError_t launch_stream_step(const StreamArgs& A, bool pair, int flux, int depth, hipStream_t s)
+{
+    if (A.ksteps < 1 || A.ksteps > depth || (pair && depth != 4 && !A.z)) return hipErrorInvalidValue;
     const dim3 grid((unsigned)((A.n / TT) * (A.n / TT)), (unsigned)A.count);
     if (pair) {
-        if (flux == DK_FLUX_CENTRAL) hipLaunchKernelGGL((stream_kernel<DK_FLUX_CENTRAL, true>), grid, dim3(THREADS), 0, s, A);
-        else hipLaunchKernelGGL((stream_kernel<DK_FLUX_STAGGERED, true>), grid, dim3(THREADS), 0, s, A);
-    } else {
-        if (flux == DK_FLUX_CENTRAL) hipLaunchKernelGGL((stream_kernel<DK_FLUX_CENTRAL, false>), grid, dim3(THREADS), 0, s, A);
-        else hipLaunchKernelGGL((stream_kernel<DK_FLUX_STAGGERED, false>), grid, dim3(THREADS), 0, s, A);
+        if (flux == DK_FLUX_CENTRAL) return launch_depth<DK_FLUX_CENTRAL, true>(A, depth, grid, s);
+        return launch_depth<DK_FLUX_STAGGERED, true>(A, depth, grid, s);
     }
+    if (flux == DK_FLUX_CENTRAL) return launch_depth<DK_FLUX_CENTRAL, false>(A, depth, grid, s);
+    return launch_depth<DK_FLUX_STAGGERED, false>(A, depth, grid, s);
+}
+
+hipError_t launch_stream_coarse(int nc, int count, float a, float kc, int flux, const float* rho_in, const float* cmp_in,
+                                const float* z, float* rho_out, float* cmp_out, hipStream_t s)
+{
+    const size_t total = (size_t)nc * nc * count;
+    const dim3 grid((unsigned)((total + 255) / 256));
+    if (flux == DK_FLUX_CENTRAL)
+        hipLaunchKernelGGL((stream_coarse_kernel<DK_FLUX_CENTRAL>), grid, dim3(256), 0, s, nc, total, a, kc, rho_in,
+                           cmp_in, (const float2*)z, rho_out, cmp_out);
+    else
+        hipLaunchKernelGGL((stream_coarse_kernel<DK_FLUX_STAGGERED>), grid, dim3(256), 0, s, nc, total, a, kc, rho_in,
+                           cmp_in, (const float2*)z, rho_out, cmp_out);
     return hipGetLastError();
 }
 

@@ -1,7 +1,8 @@
-"""The HBM-streaming level kernel (grids beyond 128^2; 4-step temporal blocking) against the
-resident kernel on grids both can run (same fields bit for bit, so the observables agree to
-the FP64 reduction order), and against the FP64 oracle on 256^2 and 1024^2 grids with short
-horizons (tolerance as for the resident kernel, 1e-5 of the batch RMS)."""
+"""The HBM-streaming level kernel (grids beyond 128^2; temporal blocking of 1, 2, 4 or 8 fine
+steps per launch) against the resident kernel on grids both can run (same fields bit for bit,
+so the observables agree to the FP64 reduction order), across its depths (bit-identical
+per-sample values), and against the FP64 oracle on 256^2 and 1024^2 grids with short horizons
+(tolerance as for the resident kernel, 1e-5 of the batch RMS)."""
 import numpy as np
 import pytest
 
@@ -36,9 +37,75 @@ def test_stream_matches_resident(level, flux):
         torch.cuda.synchronize()
         a, b = a.cpu().numpy(), b.cpu().numpy()
         assert np.allclose(a, b, rtol=1e-11, atol=1e-13), (coupled, np.max(np.abs(a - b)))
-        assert st.stats()[-1]["rows"] == -1 or any(s["rows"] == -1 for s in st.stats())
+        assert any(s["rows"] == -4 for s in st.stats())          # streamed at the default depth
     res.close()
     st.close()
+
+
+@pytest.mark.parametrize("flux", [W.FLUX_CENTRAL, W.FLUX_STAGGERED])
+@pytest.mark.parametrize("n0,steps", [(32, 12), (64, 20)])
+def test_stream_depths_bit_identical(n0, steps, flux):
+    """Depths 1, 2 and 8 (restricted-noise sums through HBM, separate coarse step; at depth 8 a
+    launch completes two coarse steps, and with 12 or 20 fine steps the last launch only one)
+    against depth 4 (coarse step fused): identical per-sample values, coupled and single, on the
+    64^2 / 32^2 and 128^2 / 64^2 pairs."""
+    level = 1
+    p = W.config2(N=3e3).with_(flux=flux, n0=n0, levels=2)
+    p = p.with_(T=p.tau(level) * steps)
+    assert p.steps(level) == steps
+    banner(f"stream depths n={p.n(level)} steps={steps} flux={flux}")
+    ctx = dk.Context(0)
+    ctx.set_streaming(True)
+    for coupled in (True, False):
+        vals = {}
+        for depth in (4, 1, 2, 8):
+            ctx.reset()
+            ctx.set_stream_depth(depth)
+            if coupled:
+                _, ps = dk.level_pair(p, level, 11, 37, per_sample=True, ctx=ctx)
+            else:
+                _, ps = dk.mc_level(p, level, 11, 37, per_sample=True, ctx=ctx)
+            torch.cuda.synchronize()
+            vals[depth] = ps.cpu()
+            assert [s["rows"] for s in ctx.stats()] == [-depth]
+        for depth in (1, 2, 8):
+            assert torch.equal(vals[depth], vals[4]), (coupled, depth, (vals[depth] - vals[4]).abs().max())
+    with pytest.raises(dk.DKError):
+        ctx.set_stream_depth(3)
+    ctx.close()
+
+
+def test_stream_depth_tuning():
+    """A streamed job of >= 1e11 cell updates (config-3 finest pair, 256^2, 32768 fine steps, 48
+    pairs) times the four depths once, keeps the fastest, lists it in the tuning JSON, and gives
+    the same values as a forced depth; the JSON entry loads back into a new context."""
+    p = W.config3(N=1e5)
+    level = p.levels - 1
+    assert p.n(level) == 256
+    banner("streaming depth tuning, 256^2 pair, 48 pairs")
+    auto = dk.Context(0)
+    _, a = dk.level_pair(p, level, 0, 48, per_sample=True, ctx=auto)
+    torch.cuda.synchronize()
+    js = auto.tuning_json()
+    import json
+    ent = [e for e in json.loads(js)["shapes"] if "depth" in e]
+    assert len(ent) == 1 and ent[0]["n"] == 256 and ent[0]["pair"] == 1 and ent[0]["depth"] in (1, 2, 4, 8)
+    chosen = ent[0]["depth"]
+    banner(f"tuned depth {chosen}")
+    assert [s["rows"] for s in auto.stats() if s["level"] == level] == [-chosen]
+    forced = dk.Context(0)
+    forced.set_stream_depth(4 if chosen != 4 else 2)
+    _, b = dk.level_pair(p, level, 0, 48, per_sample=True, ctx=forced)
+    torch.cuda.synchronize()
+    assert torch.equal(a.cpu(), b.cpu())
+    loaded = dk.Context(0)
+    loaded.load_tuning_json(js)
+    assert json.loads(loaded.tuning_json()) == json.loads(js)
+    bad = js.replace(f'"depth": {chosen}', '"depth": 3')
+    with pytest.raises(dk.DKError):
+        loaded.load_tuning_json(bad)
+    for c in (auto, forced, loaded):
+        c.close()
 
 
 def scaled_err(gpu, ref):
