@@ -41,6 +41,9 @@ STEPS_ROUND_T = 1     # M_0 = round(T / tau_0); the effective final time is M_0 
 PREC_F32 = 0
 PREC_F64 = 1
 
+COUPLING_NN = 0        # right-most nearest-neighbour coupling, h_(l-1) = 2 h_l (Sec. 3.2)
+COUPLING_FOURIER = 1   # Fourier coupling, h_(l-1) = 3 h_l (Sec. 3.1)
+
 TAG_MLMC = 0
 TAG_MC = 1
 TAG_CV_TRAIN = 2
@@ -96,10 +99,16 @@ class Problem:
     obs: List[Obs] = field(default_factory=list)
     primary: int = 0
     seed: int = 0
+    coupling: int = COUPLING_NN
 
     # --- derived level data (pure bookkeeping, no method arithmetic) ---
+    @property
+    def ratio(self) -> int:
+        """h_(l-1) / h_l: 2 for the NN coupling, 3 for the Fourier coupling (Sec. 3)."""
+        return 3 if self.coupling == COUPLING_FOURIER else 2
+
     def n(self, level: int) -> int:
-        return self.n0 << level
+        return self.n0 * self.ratio ** level
 
     def h(self, level: int) -> float:
         return self.box / self.n(level)
@@ -112,7 +121,7 @@ class Problem:
         r = int(round(m0))
         if self.steps_policy == STEPS_EXACT and abs(m0 - r) > 1e-9 * max(1.0, r):
             raise ValueError(f"T/tau_0 = {m0} is not an integer")
-        return r << (2 * level)
+        return r * self.ratio ** (2 * level)
 
     def with_(self, **kw) -> "Problem":
         return replace(self, **kw)
@@ -253,3 +262,12 @@ def paper_reg(N: float = 2e9) -> Problem:
 def paper_irreg(N: float = 2e9) -> Problem:
     """Sec. 7 with the irregular datum Z^-1 exp(-(sin^2(x - pi/2) + sin^2(y - 3 pi/2))/(2 * 0.1))."""
     return _paper_problem(N, 0.0, 1.0, 0.1)
+
+
+def paper_fourier(N: float = 2e9, irregular: bool = False) -> Problem:
+    """The Sec. 7 setting with the Fourier coupling of Sec. 3.1 instead of the NN coupling: the
+    same torus, datum, observable, T and tau/h^2, but h_(l-1) = 3 h_l, so the hierarchy is
+    4 x 4, 12 x 12, 36 x 36, 108 x 108 (1, 9, 81, 729 steps; h_min = 2 pi / 108, close to the
+    NN hierarchy's 2 pi / 128)."""
+    base = paper_irreg(N) if irregular else paper_reg(N)
+    return base.with_(coupling=COUPLING_FOURIER, levels=4)

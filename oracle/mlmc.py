@@ -6,7 +6,10 @@ Follows Cornalba & Fischer, Sec. 4 eq. (MLMCEstimator) and Sec. 7 "Types of expe
 * optimal sample counts, eq. (opt_M_ell):
       M_l = ceil( 2 eps^{-2} sqrt(V_l / C_l) sum_k sqrt(V_k C_k) );
 * convergence test, eq. (convergence_criterion):
-      max_{j in {0,1,2}} 2^{-j alpha} |E[P_{L-j} - P_{L-j-1}]| / (2^alpha - 1) < eps / sqrt(2);
+      max_{j in {0,1,2}} 2^{-j alpha} |E[P_{L-j} - P_{L-j-1}]| / (2^alpha - 1) < eps / sqrt(2),
+  where 2 is the refinement ratio h_{l-1}/h_l of the NN coupling; with the Fourier coupling
+  (ratio 3) the same test uses 3 in place of 2 (the bias is assumed to fall by ratio^alpha
+  per level);
 * Algorithm 1: start with L = 2 and a target of M_bar samples on levels 0, 1, 2; while extra
   samples are needed, draw them, update V_l, recompute the optimal M_l and test convergence;
   if not converged, add a level with an initial target.
@@ -48,14 +51,13 @@ def optimal_M(eps: float, V: np.ndarray, Cst: np.ndarray) -> np.ndarray:
     return np.ceil(2.0 * eps ** -2 * np.sqrt(V / Cst) * s).astype(np.int64)
 
 
-def converged(Yhat: np.ndarray, L: int, eps: float, alpha: float = 2.0) -> bool:
+def converged(Yhat: np.ndarray, L: int, eps: float, alpha: float = 2.0, ratio: float = 2.0) -> bool:
     """Eq. (convergence_criterion) on levels L, L-1, L-2."""
-    rem = max(2.0 ** (-j * alpha) * abs(Yhat[L - j]) for j in range(3)) / (2.0 ** alpha - 1.0)
-    return rem < eps / math.sqrt(2.0)
+    return remainder(Yhat, L, alpha, ratio) < eps / math.sqrt(2.0)
 
 
-def remainder(Yhat: np.ndarray, L: int, alpha: float = 2.0) -> float:
-    return max(2.0 ** (-j * alpha) * abs(Yhat[L - j]) for j in range(3)) / (2.0 ** alpha - 1.0)
+def remainder(Yhat: np.ndarray, L: int, alpha: float = 2.0, ratio: float = 2.0) -> float:
+    return max(ratio ** (-j * alpha) * abs(Yhat[L - j]) for j in range(3)) / (ratio ** alpha - 1.0)
 
 
 @dataclass
@@ -74,7 +76,7 @@ class Alg1Result:
 
 def algorithm1(sampler: Callable[[int, int, int], np.ndarray], eps: float, L_max: int,
                cost: Callable[[int], float], M_bar: int = 1000, L_start: int = 2,
-               alpha: float = 2.0) -> Alg1Result:
+               alpha: float = 2.0, ratio: float = 2.0) -> Alg1Result:
     L = L_start
     done = [0] * (L_max + 1)
     s1 = [0.0] * (L_max + 1)
@@ -88,7 +90,7 @@ def algorithm1(sampler: Callable[[int, int, int], np.ndarray], eps: float, L_max
         extra = [max(0, target[l] - done[l]) for l in range(L + 1)]
         if sum(extra) == 0:
             Yhat = np.array([s1[l] / done[l] for l in range(L + 1)])
-            if converged(Yhat, L, eps, alpha):
+            if converged(Yhat, L, eps, alpha, ratio):
                 conv = True
                 break
             if L == L_max:

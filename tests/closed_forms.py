@@ -12,7 +12,11 @@ pins for the oracle (they share no code with it):
   E[X^2] = sum_m tau (E[rho^m]^+, |grad_h phi^{m+1}|^2)_h for X = sqrt(N)(rho^M - rho_bar^M, phi)_h
   (with equality to the mean-field value when rho stays positive);
 * for the NN coupling of Sec. 3.2 the same computation on the pair gives the level
-  variance of eq. (eqn:VarOfLvlPrelim) with rho replaced by the mean field.
+  variance of eq. (eqn:VarOfLvlPrelim) with rho replaced by the mean field;
+* for the Fourier coupling of Sec. 3.1 the coarse noise is the fine noise projected onto the
+  coarse frequencies (summed over the 9 fine steps) and read at the coarse nodes; the
+  projection is written here in real space as a sum of cosines (restriction_1d), and the
+  level variance follows as for the NN coupling with the lift replaced by its transpose.
 """
 from __future__ import annotations
 
@@ -144,6 +148,59 @@ def pair_variance_linear(p: W.Problem, level: int, phi: W.Field, flux: int | Non
         mfx, mfy = mobility(rf, flux)
         dx = np.sqrt(mfx) * gfx - cx
         dy = np.sqrt(mfy) * gfy - cy
+        V += tf * hf * hf * float(np.sum(dx * dx + dy * dy))
+    return V
+
+
+def restriction_1d(nf: int, nc: int) -> np.ndarray:
+    """Real-space kernel K[i_c, i] of the projection of a fine grid function onto the coarse
+    frequencies {-nc/2, .., nc/2} (weight 2^{-1/2} on +-nc/2), read at coarse node 3 i_c:
+    K = (1/nf) [1 + 2 sum_{k=1}^{nc/2-1} cos(2 pi k d / nf) + sqrt(2) cos(pi nc d / nf)],
+    d = 3 i_c - i.  In 2-D the projection is K (x) K."""
+    assert nf == 3 * nc and nc % 2 == 0
+    d = 3 * np.arange(nc)[:, None] - np.arange(nf)[None, :]
+    K = np.ones((nc, nf))
+    for k in range(1, nc // 2):
+        K += 2.0 * np.cos(2 * math.pi * k * d / nf)
+    K += math.sqrt(2.0) * np.cos(math.pi * nc * d / nf)
+    return K / nf
+
+
+def pair_variance_linear_fourier(p: W.Problem, level: int, phi: W.Field) -> float:
+    """Var(X_f - X_c) for the centred, sqrt(N)-scaled linear observable of the Fourier-coupled
+    pair (h_c = 3 h_f, 9 fine steps per coarse step, central flux) in the high-density limit.
+    X_f = -sum_{m,y,r} h_f sqrt(tau_f) g_f^m(y) z^m_r(y) with g = sqrt(rho_bar) grad phi (the
+    adjoint form of the noise term); the coarse noise is h_f^{-1} sqrt(tau_f) (K x K) applied to
+    the fine normals summed over the coarse step, so X_c has the coefficient
+    h_f sqrt(tau_f) 9 (K x K)^T g_c on every fine normal of that step."""
+    nf, nc = p.n(level), p.n(level - 1)
+    hf, hc = p.h(level), p.h(level - 1)
+    tf = p.tau(level)
+    Mf = p.steps(level)
+    Mc = Mf // 9
+    K = restriction_1d(nf, nc)
+    lamf, lamc = heat_multiplier(nf, p.mu), heat_multiplier(nc, p.mu)
+    rf0 = np.fft.fft2(field_np(p.rho0, p.box, nf))
+    rc0 = np.fft.fft2(field_np(p.rho0, p.box, nc))
+    ff0 = np.fft.fft2(field_np(phi, p.box, nf))
+    fc0 = np.fft.fft2(field_np(phi, p.box, nc))
+    V = 0.0
+    lifted = None
+    for m in range(Mf):
+        mc = m // 9
+        if m % 9 == 0:
+            rc = np.real(np.fft.ifft2(rc0 * lamc ** mc))
+            phc = np.real(np.fft.ifft2(fc0 * lamc ** (Mc - mc - 1)))
+            gcx, gcy = grad(phc, hc, W.FLUX_CENTRAL)
+            sq = np.sqrt(np.maximum(rc, 0.0))
+            # [y, x] arrays: (K x K)^T g = K^T g K
+            lifted = (9.0 * K.T @ (sq * gcx) @ K, 9.0 * K.T @ (sq * gcy) @ K)
+        rf = np.real(np.fft.ifft2(rf0 * lamf ** m))
+        phf = np.real(np.fft.ifft2(ff0 * lamf ** (Mf - m - 1)))
+        gfx, gfy = grad(phf, hf, W.FLUX_CENTRAL)
+        sq = np.sqrt(np.maximum(rf, 0.0))
+        dx = sq * gfx - lifted[0]
+        dy = sq * gfy - lifted[1]
         V += tf * hf * hf * float(np.sum(dx * dx + dy * dy))
     return V
 
