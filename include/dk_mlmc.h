@@ -9,11 +9,12 @@
  *   operators          5-point Laplacian and central divergence (Sec. 7, "Differential
  *                      operators"); DK_FLUX_STAGGERED selects a forward difference of edge
  *                      fluxes with the edge-averaged density under the square root
- *   level hierarchy    h_l = box / (n0 2^l), tau_l = mu h_l^2 (eq. cfl_preserved),
- *                      M_l = T / tau_l steps
+ *   level hierarchy    h_l = box / (n0 2^l) (box / (n0 3^l) for the Fourier coupling),
+ *                      tau_l = mu h_l^2 (eq. cfl_preserved), M_l = T / tau_l steps
  *   coupling           NN ("Right-Most Nearest Neighbours"), Sec. 3.2: coarse Brownian
  *                      increments are 2^{-d/2} times the sum of the fine increments over the
- *                      2x2 right-most block and over the 4 fine steps of one coarse step
+ *                      2x2 right-most block and over the 4 fine steps of one coarse step;
+ *                      or Fourier, Sec. 3.1 (h_{l-1} = 3 h_l; DK_COUPLING_FOURIER below)
  *   observables        P_l of eq. (eqn_MLMCLevels): psi( s ((rho_l^T, I_h phi)_h - c_l) ),
  *                      c_l = (rho_bar_l^T, I_h phi)_h from the discrete mean field (Sec. 3)
  *   estimator          eq. (MLMCEstimator) and Algorithm 1 (Sec. 7) with eq. (opt_M_ell)
@@ -86,6 +87,17 @@ extern "C" {
 #define DK_MAX_LEVELS 12
 #define DK_MAX_MODES 64
 
+/* Level coupling (Sec. 3).  NN: right-most nearest neighbours, h_{l-1} = 2 h_l, tau_{l-1} =
+ * 4 tau_l (Sec. 3.2; every kernel).  FOURIER: h_{l-1} = 3 h_l, tau_{l-1} = 9 tau_l (Sec. 3.1):
+ * grids n_l = n0 3^l with n0 in {4, 8} up to 108 x 108 (FP32 or FP64 state, central flux);
+ * the fine level runs the same nodal noise as every level, the coarse level the fine normals
+ * summed over its 9 fine steps and projected onto the coarse frequencies (on the coarse
+ * Nyquist frequency the two fine aliases enter with weight 2^{-1/2}), read at the coarse
+ * nodes.  Pair cost: n^2 M (1 + 1/81) cell updates; the bias test of Algorithm 1 uses ratio
+ * 3 in place of 2. */
+#define DK_COUPLING_NN 0
+#define DK_COUPLING_FOURIER 1
+
 /* ---- problem statement (Sec. 2, Sec. 3, Sec. 7) ---- */
 typedef struct { double amp, kx, ky, phase; } dk_mode;
 
@@ -123,6 +135,8 @@ typedef struct {
     const dk_obs* obs;        /* host array [n_obs]                                         */
     dk_field rho0;            /* initial mean-field profile; rho^0 = I_h rho0 on every level */
     uint64_t seed;            /* Philox key                                                 */
+    int32_t coupling;         /* DK_COUPLING_NN (default) or DK_COUPLING_FOURIER           */
+    int32_t reserved;
 } dk_problem;
 
 /* ---- per-level moment sums ---- */

@@ -34,7 +34,8 @@ class dk_problem(C.Structure):
     _fields_ = [("d", C.c_int32), ("n0", C.c_int32), ("levels", C.c_int32), ("steps_policy", C.c_int32),
                 ("box", C.c_double), ("mu", C.c_double), ("T", C.c_double), ("N", C.c_double),
                 ("flux", C.c_int32), ("precision", C.c_int32), ("n_obs", C.c_int32), ("primary_obs", C.c_int32),
-                ("obs", C.POINTER(dk_obs)), ("rho0", dk_field), ("seed", C.c_uint64)]
+                ("obs", C.POINTER(dk_obs)), ("rho0", dk_field), ("seed", C.c_uint64),
+                ("coupling", C.c_int32), ("reserved", C.c_int32)]
 
 
 class dk_moments(C.Structure):

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "dk_cnn.h"
+#include "dk_fourier.h"
 #include "dk_internal.h"
 #include "dk_round.h"
 #include "dk_stream.h"
@@ -89,7 +90,7 @@ uint64_t problem_hash(const dk_problem* p)
 {
     Hasher H;
     H.val(p->d); H.val(p->n0); H.val(p->levels); H.val(p->steps_policy); H.val(p->box); H.val(p->mu);
-    H.val(p->T); H.val(p->N); H.val(p->flux); H.val(p->precision); H.val(p->n_obs);
+    H.val(p->T); H.val(p->N); H.val(p->flux); H.val(p->precision); H.val(p->n_obs); H.val(p->coupling);
     H.field(p->rho0);
     for (int j = 0; j < p->n_obs; ++j) {
         H.field(p->obs[j].phi); H.val(p->obs[j].centre); H.val(p->obs[j].scale_sqrtN); H.val(p->obs[j].psi);
@@ -120,6 +121,20 @@ long steps0_of(const dk_problem* p)
     return m;
 }
 
+bool fourier(const dk_problem* p) { return p->coupling == DK_COUPLING_FOURIER; }
+// h_{l-1} / h_l: 2 (NN coupling) or 3 (Fourier coupling)
+int level_ratio(const dk_problem* p) { return fourier(p) ? 3 : 2; }
+long ipow(long b, int e)
+{
+    long r = 1;
+    while (e-- > 0) r *= b;
+    return r;
+}
+int level_n(const dk_problem* p, int l) { return (int)(p->n0 * ipow(level_ratio(p), l)); }
+long level_steps(const dk_problem* p, long steps0, int l) { return steps0 * ipow(level_ratio(p), 2 * l); }
+// coarse work of a pair relative to its fine work: ratio^{-(d+2)}
+double pair_factor(const dk_problem* p) { return fourier(p) ? 1.0 + 1.0 / 81.0 : 1.0 + 1.0 / 16.0; }
+
 int validate(const dk_problem* p)
 {
     if (!p) return fail(DK_EINVAL, "problem is NULL");
@@ -143,11 +158,21 @@ int validate(const dk_problem* p)
         if (rc) return rc;
         if (p->obs[j].psi != DK_PSI_ID && p->obs[j].psi != DK_PSI_SQUARE) return fail(DK_EINVAL, "obs %d: unknown psi", j);
     }
+    if (p->coupling != DK_COUPLING_NN && p->coupling != DK_COUPLING_FOURIER)
+        return fail(DK_EINVAL, "unknown coupling %d", p->coupling);
+    if (fourier(p)) {
+        if (p->flux != DK_FLUX_CENTRAL) return fail(DK_EUNSUPPORTED, "the Fourier coupling runs the central flux only");
+        if (p->levels > 6) return fail(DK_EINVAL, "levels = %d: the Fourier hierarchy has at most 6 levels", p->levels);
+        for (int l = 0; l < p->levels; ++l)
+            if (!dk::fourier_supported(level_n(p, l), l >= 1))
+                return fail(DK_EUNSUPPORTED, "Fourier coupling: no kernel for the %d x %d grid of level %d (n0 = 4 or 8, "
+                                             "at most 108 x 108)", level_n(p, l), level_n(p, l), l);
+    }
     const long m0 = steps0_of(p);
     if (m0 < 0) return (int)m0;
-    const long mtop = m0 << (2 * (p->levels - 1));
+    const long mtop = level_steps(p, m0, p->levels - 1);
     if (mtop > (1l << 30)) return fail(DK_EINVAL, "too many time steps (%ld) on the finest level", mtop);
-    if ((long)p->n0 << (p->levels - 1) > 4096) return fail(DK_EINVAL, "finest grid larger than 4096");
+    if (!fourier(p) && (long)p->n0 << (p->levels - 1) > 4096) return fail(DK_EINVAL, "finest grid larger than 4096");
     return DK_OK;
 }
 
@@ -190,6 +215,7 @@ struct LevelTables {
     bool have_centre = false;
     DevBuf rbar;                  // FP64 discrete mean field at the final time [n*n]
     bool have_rbar = false;
+    DevBuf fourier_K;             // Fourier pairs with this fine level: projection kernel [n/3][n], state type
 };
 
 struct ProblemTables {
@@ -241,6 +267,7 @@ struct dk_context {
     DevBuf scratch_c;      // inner products
     DevBuf st_f[2][2], st_c[2][2];   // streaming state: [buffer][rho, cmp] fine / coarse
     DevBuf st_z;                     // streaming pairs: restricted-noise sums of split depths
+    DevBuf fourier_scratch;          // Fourier pairs: per-block sums and half-projected sums
     std::vector<double> host_mom;
     // learned control variate
     dk::cnn::Workspace cnn;
@@ -322,11 +349,11 @@ int ensure_level(dk_context* ctx, const dk_problem* p, int level, LevelTables** 
     if (level < 0 || level >= p->levels) return fail(DK_EINVAL, "level %d outside [0, %d)", level, p->levels);
     if (PT.level[level]) { *out = PT.level[level].get(); return DK_OK; }
     std::unique_ptr<LevelTables> T(new LevelTables());
-    const int n = p->n0 << level;
+    const int n = level_n(p, level);
     T->n = n;
     T->h = p->box / n;
     T->tau = p->mu * T->h * T->h;
-    T->steps = steps0_of(p) << (2 * level);
+    T->steps = level_steps(p, steps0_of(p), level);
     const bool f64 = p->precision == DK_PREC_F64;
     const int nobs = p->n_obs;
     int rc = T->rho0.ensure((f64 ? 8 : 4) * (size_t)n * n);
@@ -683,6 +710,97 @@ int run_stream(dk_context* ctx, const dk_problem* p, int level, bool pair, uint6
     return DK_OK;
 }
 
+// Levels of a Fourier-coupled hierarchy (Sec. 3.1): the projection kernel of the pair, then
+// chunks of samples with blocks striding over each chunk, the moments in chunk order.
+int run_fourier(dk_context* ctx, const dk_problem* p, int level, bool pair, uint64_t first, uint64_t count,
+                const dk::LevelArgs& A, LevelTables* Tf, LevelTables* Tc, dk_moments* sums_out, double* per_sample_out,
+                hipStream_t s, double* cell_updates, uint64_t nchunks, uint64_t ch, size_t mom_stride)
+{
+    const int nf = A.nf, nc = nf / 3, nobs = p->n_obs;
+    const bool f64 = p->precision == DK_PREC_F64;
+    const size_t esize = f64 ? 8 : 4;
+    int rc;
+    if (pair && !Tf->fourier_K.p) {
+        // K[ic][i] = (1/nf) [1 + 2 sum_{k=1}^{nc/2-1} cos(2 pi k d / nf) + sqrt(2) cos(pi nc d / nf)], d = 3 ic - i:
+        // projection onto the coarse frequencies (weight 2^{-1/2} on +-nc/2) read at coarse node ic
+        std::vector<double> K((size_t)nc * nf);
+        const double pi = 3.14159265358979323846;
+        for (int ic = 0; ic < nc; ++ic)
+            for (int i = 0; i < nf; ++i) {
+                const double d = (double)(3 * ic - i);
+                double v = 1.0;
+                for (int k = 1; k < nc / 2; ++k) v += 2.0 * std::cos(2.0 * pi * k * d / nf);
+                v += std::sqrt(2.0) * std::cos(pi * nc * d / nf);
+                K[(size_t)ic * nf + i] = v / nf;
+            }
+        if ((rc = Tf->fourier_K.ensure(esize * K.size()))) return rc;
+        std::vector<float> Kf(K.begin(), K.end());
+        if (f64) HIP_TRY(hipMemcpyAsync(Tf->fourier_K.p, K.data(), 8 * K.size(), hipMemcpyHostToDevice, s));
+        else HIP_TRY(hipMemcpyAsync(Tf->fourier_K.p, Kf.data(), 4 * Kf.size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    dk::FourierArgs F{};
+    F.nf = nf; F.level_id = level; F.tag = A.tag; F.seed = A.seed; F.steps = A.steps; F.n_obs = nobs;
+    F.a = A.a; F.kf = A.kf;
+    // projected sums have unit variance per coarse node: kc = kf h_f / h_c
+    F.kc = pair ? noise_coeff(p, Tc->h, std::sqrt(Tf->tau) * Tc->h / Tf->h) : 0.0;
+    F.h2f = A.h2f; F.h2c = A.h2c;
+    F.rho0_f = A.rho0_f; F.rho0_c = A.rho0_c; F.phi_f = A.phi_f; F.phi_c = A.phi_c; F.obs_f = A.obs_f; F.obs_c = A.obs_c;
+    F.K = pair ? Tf->fourier_K.p : nullptr;
+    const int grid = dk::fourier_grid(nf, p->precision, ch);
+    if (pair && (rc = ctx->fourier_scratch.ensure(esize * dk::fourier_scratch_elems(nf) * (size_t)grid))) return rc;
+    F.scratch = pair ? ctx->fourier_scratch.p : nullptr;
+    while (ctx->ev_pool.size() < 2 * nchunks) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        ctx->ev_pool.push_back(e);
+    }
+    const bool log = std::getenv("DK_LOG") != nullptr;
+    for (uint64_t k = 0; k < nchunks; ++k) {
+        const uint64_t b = k * ch;
+        const uint64_t c = std::min(ch, count - b);
+        F.first = first + b;
+        F.count = c;
+        F.out = per_sample_out ? per_sample_out + b * nobs * 2 : (double*)ctx->per_sample.p;
+        HIP_TRY(hipEventRecord(ctx->ev_pool[2 * k], s));
+        HIP_TRY(dk::launch_fourier(F, p->precision, pair, std::min(grid, dk::fourier_grid(nf, p->precision, c)), s));
+        HIP_TRY(hipEventRecord(ctx->ev_pool[2 * k + 1], s));
+        HIP_TRY(dk::launch_moments(F.out, c, nobs, (double*)ctx->moments.p + k * mom_stride, s));
+        if (log && nchunks > 1) {
+            HIP_TRY(hipEventSynchronize(ctx->ev_pool[2 * k + 1]));
+            std::fprintf(stderr, "[dk] Fourier level %d%s launch %llu/%llu (%llu samples)\n", level, pair ? " pair" : "",
+                         (unsigned long long)(k + 1), (unsigned long long)nchunks, (unsigned long long)c);
+            std::fflush(stderr);
+        }
+    }
+    ctx->host_mom.resize(mom_stride * nchunks);
+    HIP_TRY(hipMemcpyAsync(ctx->host_mom.data(), ctx->moments.p, sizeof(double) * mom_stride * nchunks,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const double per = (double)nf * nf * (double)A.steps * (pair ? pair_factor(p) : 1.0);
+    {
+        KStat& st = ctx->stats[std::make_pair(level, pair ? 1 : 0)];
+        for (uint64_t k = 0; k < nchunks; ++k) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, ctx->ev_pool[2 * k], ctx->ev_pool[2 * k + 1]));
+            st.ms += ms;
+        }
+        st.launches += nchunks;
+        st.samples += count;
+        st.rows = 0;   // Fourier kernel: the fine state in LDS, no tile shapes
+        st.cells += per * (double)count;
+    }
+    for (uint64_t k = 0; k < nchunks; ++k) {
+        const uint64_t c = std::min(ch, count - k * ch);
+        for (int j = 0; j < nobs; ++j) merge_moments(sums_out[j], &ctx->host_mom[k * mom_stride + j * DK_NMOM * 2], c);
+    }
+    for (int j = 0; j < nobs; ++j)
+        for (int m = 0; m < DK_NMOM; ++m)
+            if (!std::isfinite(mom_value(sums_out[j], m))) return fail(DK_ENUMERIC, "non-finite sample values on level %d", level);
+    if (cell_updates) *cell_updates += per * (double)count;
+    return DK_OK;
+}
+
 // Run samples [first, first+count) of level `level` (coupled pair if `pair`), reduce the
 // per-sample values in chunk order and return per-observable moments.
 int run_level(dk_context* ctx, const dk_problem* p, int level, bool pair, uint64_t first, uint64_t count,
@@ -695,8 +813,10 @@ int run_level(dk_context* ctx, const dk_problem* p, int level, bool pair, uint64
     if (level < 0 || level >= p->levels) return fail(DK_EINVAL, "level %d outside [0, %d)", level, p->levels);
     if (count > 0 && first + count < first) return fail(DK_EINVAL, "sample range overflows");
     if (first + count > (1ull << 48)) return fail(DK_EINVAL, "sample index beyond 2^48");
-    const int nf = p->n0 << level;
-    const bool stream = !dk::level_supported(nf) || (ctx->force_stream && dk::stream_supported(nf));
+    const int nf = level_n(p, level);
+    const bool four = fourier(p);
+    const bool stream = !four && (!dk::level_supported(nf) || (ctx->force_stream && dk::stream_supported(nf)));
+    if (four && (field_f || field_c)) return fail(DK_EUNSUPPORTED, "field output is not available for the Fourier coupling");
     if (stream) {
         if (!dk::stream_supported(nf))
             return fail(DK_EUNSUPPORTED, "grid %d x %d: neither the resident nor the streaming kernel supports it", nf, nf);
@@ -714,7 +834,7 @@ int run_level(dk_context* ctx, const dk_problem* p, int level, bool pair, uint64
     const int nobs = p->n_obs;
     for (int j = 0; j < nobs; ++j) std::memset(&sums_out[j], 0, sizeof(dk_moments));
     if (count == 0) return DK_OK;
-    const double cells_per_sample = (double)nf * nf * (double)Tf->steps * (pair ? 1.0 + 1.0 / 16.0 : 1.0);
+    const double cells_per_sample = (double)nf * nf * (double)Tf->steps * (pair ? pair_factor(p) : 1.0);
     const uint64_t ch = chunk_size(nobs, cells_per_sample, ctx->max_launch_cells);
     const bool log = std::getenv("DK_LOG") != nullptr;
     const uint64_t nchunks = (count + ch - 1) / ch;
@@ -748,6 +868,9 @@ int run_level(dk_context* ctx, const dk_problem* p, int level, bool pair, uint64
     if (stream)
         return run_stream(ctx, p, level, pair, first, count, tag, A, sums_out, per_sample_out, s, cell_updates, nchunks, ch,
                           mom_stride);
+    if (four)
+        return run_fourier(ctx, p, level, pair, first, count, A, Tf, Tc, sums_out, per_sample_out, s, cell_updates, nchunks,
+                           ch, mom_stride);
     int variant = 0;
     rc = choose_shape(ctx, p, pair, A, count, (double)nf * nf * (double)Tf->steps * (pair ? 1.0 + 1.0 / 16.0 : 1.0), s,
                       &variant);
@@ -814,7 +937,8 @@ int run_level(dk_context* ctx, const dk_problem* p, int level, bool pair, uint64
 int level_args(dk_context* ctx, const dk_problem* p, int l, bool pair, uint32_t tag, hipStream_t s, dk::LevelArgs* out,
                double* cells_per_sample)
 {
-    const int nf = p->n0 << l;
+    if (fourier(p)) return fail(DK_EUNSUPPORTED, "the Fourier coupling runs level by level");
+    const int nf = level_n(p, l);
     LevelTables *Tf = nullptr, *Tc = nullptr;
     int rc = ensure_level(ctx, p, l, &Tf, s);
     if (rc) return rc;
@@ -975,8 +1099,8 @@ int run_round(dk_context* ctx, const dk_problem* p, int L, const uint64_t* first
 // ------------------------------------------------------------------------------------------
 bool round_eligible(const dk_problem* p, int l, bool force_stream)
 {
-    const int nf = p->n0 << l;
-    return p->precision == DK_PREC_F32 && p->n_obs <= dk::round_max_obs() && !force_stream &&
+    const int nf = level_n(p, l);
+    return !fourier(p) && p->precision == DK_PREC_F32 && p->n_obs <= dk::round_max_obs() && !force_stream &&
            dk::round_kind(nf, l >= 1) >= 0;
 }
 
@@ -1158,11 +1282,12 @@ dk_mlmc_opts default_opts()
     return o;
 }
 
-double bias_remainder(const std::vector<double>& Y, int L, double alpha)
+double bias_remainder(const std::vector<double>& Y, int L, double alpha, double ratio)
 {
+    // eq. (convergence_criterion) with the refinement ratio h_{l-1}/h_l (2 in the paper)
     double r = 0.0;
-    for (int j = 0; j <= std::min(2, L); ++j) r = std::max(r, std::pow(2.0, -j * alpha) * std::fabs(Y[L - j]));
-    return r / (std::pow(2.0, alpha) - 1.0);
+    for (int j = 0; j <= std::min(2, L); ++j) r = std::max(r, std::pow(ratio, -j * alpha) * std::fabs(Y[L - j]));
+    return r / (std::pow(ratio, alpha) - 1.0);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1286,7 +1411,7 @@ typedef std::function<void(int, std::vector<double>&)> cost_measure;
 
 int alg1_core(double eps, int L_max, const double* cost, const dk_mlmc_opts& o, dk_level_sampler sampler, void* user,
               dk_mlmc_result* out, round_sampler rsampler = nullptr, const CkptHooks* ck = nullptr,
-              const cost_measure* measure = nullptr)
+              const cost_measure* measure = nullptr, double ratio = 2.0)
 {
     if (!(eps > 0)) return fail(DK_EINVAL, "eps must be > 0");
     if (L_max < 0 || L_max >= DK_MAX_LEVELS) return fail(DK_EINVAL, "L_max out of range");
@@ -1336,7 +1461,7 @@ int alg1_core(double eps, int L_max, const double* cost, const dk_mlmc_opts& o, 
         if (!need) {
             stats(L);
             if (L >= 2 || L == L_max) {
-                if (bias_remainder(Y, L, o.alpha) < eps / std::sqrt(2.0)) { conv = true; break; }
+                if (bias_remainder(Y, L, o.alpha, ratio) < eps / std::sqrt(2.0)) { conv = true; break; }
             }
             if (L == L_max) { conv = false; break; }
             L += 1;
@@ -1416,7 +1541,7 @@ int alg1_core(double eps, int L_max, const double* cost, const dk_mlmc_opts& o, 
     out->L = L;
     out->converged = conv ? 1 : 0;
     out->rounds = rounds;
-    out->bias_est = bias_remainder(Y, L, o.alpha);
+    out->bias_est = bias_remainder(Y, L, o.alpha, ratio);
     out->rmse_est = std::sqrt(var + out->bias_est * out->bias_est);
     return conv ? DK_OK : DK_WARN_NOT_CONVERGED;
 }
@@ -1592,10 +1717,11 @@ int gpu_round(void* user, int L, const uint64_t* first, const uint64_t* count, d
     const int nobs = G.p->n_obs;
     std::vector<uint64_t> cnt(count, count + L + 1);
     for (int l = 0; l <= L; ++l) {
-        const int nf = G.p->n0 << l;
+        const int nf = level_n(G.p, l);
         const bool cv = l >= 1 && G.cv_params && ((G.cv_mask >> l) & 1u);
-        const bool streamed = !dk::level_supported(nf) || (G.ctx->force_stream && dk::stream_supported(nf));
-        const bool outside = G.round_mode == 3 && G.p->precision == DK_PREC_F32 && !round_eligible(G.p, l, G.ctx->force_stream);
+        const bool streamed = !fourier(G.p) && (!dk::level_supported(nf) || (G.ctx->force_stream && dk::stream_supported(nf)));
+        const bool outside = fourier(G.p) ||
+                             (G.round_mode == 3 && G.p->precision == DK_PREC_F32 && !round_eligible(G.p, l, G.ctx->force_stream));
         if ((cv || streamed || outside || G.plain_mc) && count[l] > 0) {
             double s2[2] = {0, 0};
             const int rc = gpu_sample(user, l, first[l], count[l], s2);
@@ -1632,8 +1758,8 @@ int gpu_round(void* user, int L, const uint64_t* first, const uint64_t* count, d
 
 double level_cost(const dk_problem* p, long steps0, int level, bool pair)
 {
-    const double n = (double)(p->n0 << level);
-    return n * n * (double)(steps0 << (2 * level)) * (pair && level >= 1 ? 1.0 + 1.0 / 16.0 : 1.0);
+    const double n = (double)level_n(p, level);
+    return n * n * (double)level_steps(p, steps0, level) * (pair && level >= 1 ? pair_factor(p) : 1.0);
 }
 
 }  // namespace
@@ -1720,6 +1846,7 @@ int dk_cv_train(dk_context* ctx, const dk_problem* problem, int32_t level, uint6
     if (level < 1 || level >= problem->levels) return fail(DK_EINVAL, "control variate needs 1 <= level < levels");
     if (epochs < 1 || batch < 1 || n_train < (uint64_t)batch) return fail(DK_EINVAL, "need epochs >= 1 and n_train >= batch >= 1");
     if (!(lr > 0)) return fail(DK_EINVAL, "lr must be > 0");
+    if (fourier(problem)) return fail(DK_EUNSUPPORTED, "the control variate is built for the NN coupling");
     const int nc = problem->n0 << (level - 1);
     if (nc % 4) return fail(DK_EINVAL, "coarse grid must be a multiple of 4");
     HIP_TRY(hipSetDevice(ctx->device));
@@ -2132,6 +2259,7 @@ int dk_mlmc_estimate(dk_context* ctx, const dk_problem* problem, double eps, con
     G.tag = mc ? DK_TAG_MC : DK_TAG_MLMC;
     G.zmom.assign(problem->levels, dk_moments{});
     if (o.cv_params && !mc) {
+        if (fourier(problem)) return fail(DK_EUNSUPPORTED, "the control variate is built for the NN coupling");
         G.cv_params = o.cv_params;
         G.cv_mask = o.cv_level_mask & ~1u;
         G.cv_ratio = o.cv_ratio > 0 ? o.cv_ratio : 4;
@@ -2210,7 +2338,7 @@ int dk_mlmc_estimate(dk_context* ctx, const dk_problem* problem, double eps, con
                 if (!got[l]) C[l] = cost[l] * ref_per_cell;
         };
         rc = alg1_core(eps, problem->levels - 1, cost.data(), o, gpu_sample, &G, out,
-                       o.round_mode > 0 ? gpu_round : nullptr, &ck, &measure);
+                       o.round_mode > 0 ? gpu_round : nullptr, &ck, &measure, (double)level_ratio(problem));
         if (rc < 0) return rc;
     } else {
         // plain MC on one level: pilot, then M = ceil(2 V / eps^2) so that V / M <= eps^2 / 2
