@@ -67,13 +67,15 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 256 MiB buffer 4 times (reference for HBM byte counters)")
     ap.add_argument("--workload", default="config2",
-                    choices=["config2", "config2-mc", "config3", "config4", "config5", "paper-type1", "paper-type2"],
+                    choices=["config2", "config2-mc", "config3", "config4", "config5", "paper-type1", "paper-type2",
+                             "paper-fourier"],
                     help="config2 (default): the bench line; the others print a report line: config2-mc "
                          "plain Monte Carlo on the finest config-2 level to the same eps, config3 "
                          "low-density MLMC with persistent rounds, config4 learned control variate, "
                          "config5 streaming-kernel throughput at 256^2..1024^2, paper-type1 the paper's own "
                          "Type-1 experiment (MLMC and MC at its accuracies, speed-ups against its table), "
-                         "paper-type2 its variance-reduction factor against h_min")
+                         "paper-type2 its variance-reduction factor against h_min, paper-fourier the Fourier "
+                         "coupling against the NN coupling")
     ap.add_argument("--N", type=float, default=None, help="particle number (config3: 1e5, config5: 1e6)")
     ap.add_argument("--samples", type=int, default=32, help="config5: finest-level pairs to time")
     ap.add_argument("--cv-levels", default=None, help="config4: comma-separated levels that use the control "
@@ -145,7 +147,7 @@ def main():
     if args.workload != "config2":
         {"config2-mc": bench_config2_mc, "config3": bench_config3, "config4": bench_config4,
          "config5": bench_config5, "paper-type1": bench_paper_type1,
-         "paper-type2": bench_paper_type2}[args.workload](args)
+         "paper-type2": bench_paper_type2, "paper-fourier": bench_paper_fourier}[args.workload](args)
         return
     base = W.config2(N=1e4)
 
@@ -321,6 +323,71 @@ def bench_paper_type1(args):
                 f"tau_l=1e-3*4^(5-l), T=1.024", last["speedup_work"], "MC/MLMC work ratio at the smallest eps",
                 {"paper_speedup_at_smallest_eps": paper_speedup, "smallest_eps": last["eps"], "L_reached": last["L"],
                  "speedup_wall_at_smallest_eps": last["speedup_wall"], "runs": rows})
+
+
+def bench_paper_fourier(args):
+    """The Fourier coupling of Sec. 3.1 against the NN coupling of Sec. 3.2 in the paper's Sec. 7
+    setting (regular datum; the paper's own proposed next step).  NN: 4^2 .. 128^2 (ratio 2);
+    Fourier: 4^2, 12^2, 36^2, 108^2 (ratio 3, similar h_min).  Per N in {2e9, 2e5}:
+    1. level profile: args.samples * 125 samples per level (P = X^2, the paper's observable):
+       V_l, |Y_l|, cell updates and kernel time per sample, and the observed variance rate
+       beta_l = log(V_(l-1) / V_l) / log(ratio) (the paper predicts 4 for Fourier, 2 for NN);
+    2. Algorithm 1 at the paper's accuracies 10^-1.4 .. 10^-2.6 with either coupling: levels,
+       work (cell updates) and GPU wall time."""
+    import math
+    import torch
+    import dk_workloads as W
+    import paper_2311_08872_amd as dk
+    eps_list = [10 ** -1.4, 10 ** -1.7, 10 ** -2.0, 10 ** -2.2, 10 ** -2.4, 10 ** -2.6]
+    per_level = args.samples * 125
+    out = {}
+    ctx = dk.Context(0)
+    dk.estimate(W.paper_fourier(2e9).with_(seed=1000), 10 ** -1.4, ctx=ctx)      # warm-up (untimed)
+    dk.estimate(W.paper_reg(2e9).with_(seed=1000), 10 ** -1.4, ctx=ctx)
+    ctx.close()
+    for N in (2e9, 2e5):
+        res = {}
+        for name, p in (("nn", W.paper_reg(N)), ("fourier", W.paper_fourier(N))):
+            ctx = dk.Context(0)
+            prof = []
+            for l in range(p.levels):
+                ctx.reset()
+                mom = dk.level_pair(p, l, 0, per_level, ctx=ctx)[0]
+                torch.cuda.synchronize()
+                st = [s_ for s_ in ctx.stats() if s_["level"] == l][0]
+                prof.append({"level": l, "n": p.n(l), "steps": p.steps(l), "V": mom.var, "Y": mom.mean,
+                             "cell_updates_per_sample": st["cell_updates"] / per_level,
+                             "kernel_s_per_sample": st["kernel_ms"] / 1e3 / per_level,
+                             "cell_updates_per_s": st["cell_updates"] / (st["kernel_ms"] / 1e3)})
+            for l in range(2, p.levels):
+                prof[l]["beta"] = math.log(prof[l - 1]["V"] / prof[l]["V"]) / math.log(p.ratio)
+            vs = ", ".join("%.3g" % r_["V"] for r_ in prof)
+            bs = ", ".join("%.2f" % r_["beta"] for r_ in prof if "beta" in r_)
+            print(f"[bench] paper {name} N={N:g}: V_l = [{vs}], beta = [{bs}]", file=sys.stderr, flush=True)
+            runs = []
+            for eps in eps_list:
+                ctx.reset(drop_tables=True)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = dk.estimate(p, eps, ctx=ctx)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
+                runs.append({"eps": eps, "L": r["L"], "n_finest": p.n(r["L"]), "converged": r["converged"], "M": r["M"],
+                             "estimate": r["estimate"][0], "rmse_est": r["rmse_est"], "cell_updates": r["cell_updates"],
+                             "wall_s": wall})
+                print(f"[bench] paper {name} N={N:g} eps={eps:.3g}: L={r['L']} ({p.n(r['L'])}^2) work "
+                      f"{r['cell_updates']:.3g} cell updates, {wall:.3f} s, estimate {r['estimate'][0]:.5f}",
+                      file=sys.stderr, flush=True)
+            ctx.close()
+            res[name] = {"profile": prof, "alg1": runs}
+        res["work_ratio_nn_over_fourier"] = [a["cell_updates"] / b["cell_updates"]
+                                             for a, b in zip(res["nn"]["alg1"], res["fourier"]["alg1"])]
+        res["wall_ratio_nn_over_fourier"] = [a["wall_s"] / b["wall_s"] for a, b in zip(res["nn"]["alg1"], res["fourier"]["alg1"])]
+        out[f"N={N:g}"] = res
+    last = out["N=2e+09"]
+    _report("Fourier vs NN coupling in the paper's Sec. 7 setting (regular datum, N=2e9 and 2e5): level variances "
+            "and Algorithm 1 at eps=10^-1.4..10^-2.6", last["work_ratio_nn_over_fourier"][-1],
+            "NN/Fourier MLMC work ratio at eps=10^-2.6, N=2e9", out)
 
 
 def bench_paper_type2(args):
