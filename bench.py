@@ -68,14 +68,14 @@ def parse():
                     help="only copy a 256 MiB buffer 4 times (reference for HBM byte counters)")
     ap.add_argument("--workload", default="config2",
                     choices=["config2", "config2-mc", "config3", "config4", "config5", "paper-type1", "paper-type2",
-                             "paper-fourier"],
+                             "paper-couplings"],
                     help="config2 (default): the bench line; the others print a report line: config2-mc "
                          "plain Monte Carlo on the finest config-2 level to the same eps, config3 "
                          "low-density MLMC with persistent rounds, config4 learned control variate, "
                          "config5 streaming-kernel throughput at 256^2..1024^2, paper-type1 the paper's own "
                          "Type-1 experiment (MLMC and MC at its accuracies, speed-ups against its table), "
-                         "paper-type2 its variance-reduction factor against h_min, paper-fourier the Fourier "
-                         "coupling against the NN coupling")
+                         "paper-type2 its variance-reduction factor against h_min, paper-couplings the "
+                         "symmetric NN and the Fourier coupling against the NN coupling")
     ap.add_argument("--N", type=float, default=None, help="particle number (config3: 1e5, config5: 1e6)")
     ap.add_argument("--samples", type=int, default=32, help="config5: finest-level pairs to time")
     ap.add_argument("--cv-levels", default=None, help="config4: comma-separated levels that use the control "
@@ -147,7 +147,7 @@ def main():
     if args.workload != "config2":
         {"config2-mc": bench_config2_mc, "config3": bench_config3, "config4": bench_config4,
          "config5": bench_config5, "paper-type1": bench_paper_type1,
-         "paper-type2": bench_paper_type2, "paper-fourier": bench_paper_fourier}[args.workload](args)
+         "paper-type2": bench_paper_type2, "paper-couplings": bench_paper_couplings}[args.workload](args)
         return
     base = W.config2(N=1e4)
 
@@ -325,10 +325,12 @@ def bench_paper_type1(args):
                  "speedup_wall_at_smallest_eps": last["speedup_wall"], "runs": rows})
 
 
-def bench_paper_fourier(args):
-    """The Fourier coupling of Sec. 3.1 against the NN coupling of Sec. 3.2 in the paper's Sec. 7
-    setting (regular datum; the paper's own proposed next step).  NN: 4^2 .. 128^2 (ratio 2);
-    Fourier: 4^2, 12^2, 36^2, 108^2 (ratio 3, similar h_min).  Per N in {2e9, 2e5}:
+def bench_paper_couplings(args):
+    """The couplings of Sec. 3 in the paper's Sec. 7 setting (regular datum): the NN coupling of
+    Sec. 3.2 on the vertex grid (the paper's runs), its symmetric variant on cell centres (the
+    remark after Sec. 3.2) and the Fourier coupling of Sec. 3.1 (the paper's proposed next step).
+    NN: 4^2 .. 128^2 (ratio 2); Fourier: 4^2, 12^2, 36^2, 108^2 (ratio 3, similar h_min).  Per N
+    in {2e9, 2e5}:
     1. level profile: args.samples * 125 samples per level (P = X^2, the paper's observable):
        V_l, |Y_l|, cell updates and kernel time per sample, and the observed variance rate
        beta_l = log(V_(l-1) / V_l) / log(ratio) (the paper predicts 4 for Fourier, 2 for NN);
@@ -347,7 +349,8 @@ def bench_paper_fourier(args):
     ctx.close()
     for N in (2e9, 2e5):
         res = {}
-        for name, p in (("nn", W.paper_reg(N)), ("fourier", W.paper_fourier(N))):
+        for name, p in (("nn", W.paper_reg(N)), ("nn_cell", W.paper_reg(N).with_(grid=W.GRID_CELL)),
+                        ("fourier", W.paper_fourier(N))):
             ctx = dk.Context(0)
             prof = []
             for l in range(p.levels):
@@ -383,10 +386,12 @@ def bench_paper_fourier(args):
         res["work_ratio_nn_over_fourier"] = [a["cell_updates"] / b["cell_updates"]
                                              for a, b in zip(res["nn"]["alg1"], res["fourier"]["alg1"])]
         res["wall_ratio_nn_over_fourier"] = [a["wall_s"] / b["wall_s"] for a, b in zip(res["nn"]["alg1"], res["fourier"]["alg1"])]
+        res["work_ratio_nn_over_nn_cell"] = [a["cell_updates"] / b["cell_updates"]
+                                             for a, b in zip(res["nn"]["alg1"], res["nn_cell"]["alg1"])]
         out[f"N={N:g}"] = res
     last = out["N=2e+09"]
-    _report("Fourier vs NN coupling in the paper's Sec. 7 setting (regular datum, N=2e9 and 2e5): level variances "
-            "and Algorithm 1 at eps=10^-1.4..10^-2.6", last["work_ratio_nn_over_fourier"][-1],
+    _report("couplings in the paper's Sec. 7 setting (NN vertex, NN cell-centred, Fourier; regular datum, N=2e9 "
+            "and 2e5): level variances and Algorithm 1 at eps=10^-1.4..10^-2.6", last["work_ratio_nn_over_fourier"][-1],
             "NN/Fourier MLMC work ratio at eps=10^-2.6, N=2e9", out)
 
 

@@ -41,6 +41,9 @@ STEPS_ROUND_T = 1     # M_0 = round(T / tau_0); the effective final time is M_0 
 PREC_F32 = 0
 PREC_F64 = 1
 
+GRID_VERTEX = 0        # grid points x_i = i h
+GRID_CELL = 1          # cell centres x_i = (i + 1/2) h: the symmetric NN coupling (remark after Sec. 3.2)
+
 COUPLING_NN = 0        # right-most nearest-neighbour coupling, h_(l-1) = 2 h_l (Sec. 3.2)
 COUPLING_FOURIER = 1   # Fourier coupling, h_(l-1) = 3 h_l (Sec. 3.1)
 
@@ -100,6 +103,7 @@ class Problem:
     primary: int = 0
     seed: int = 0
     coupling: int = COUPLING_NN
+    grid: int = GRID_VERTEX
 
     # --- derived level data (pure bookkeeping, no method arithmetic) ---
     @property
@@ -109,6 +113,11 @@ class Problem:
 
     def n(self, level: int) -> int:
         return self.n0 * self.ratio ** level
+
+    @property
+    def offset(self) -> float:
+        """Grid points are x_i = (i + offset) h."""
+        return 0.5 if self.grid == GRID_CELL else 0.0
 
     def h(self, level: int) -> float:
         return self.box / self.n(level)

@@ -98,6 +98,14 @@ extern "C" {
 #define DK_COUPLING_NN 0
 #define DK_COUPLING_FOURIER 1
 
+/* Grid points.  VERTEX: x_i = i h on [0, box), so a coarse point is the fine point (2a, 2b)
+ * and the NN block B->(x) = {x + h v, v in {0,1}^2} lies to its right (Sec. 3.2).  CELL:
+ * x_i = (i + 1/2) h, the symmetric variant of the NN coupling that the remark after Sec. 3.2
+ * describes (coupling unchanged, every coarse point the centre of its 2 x 2 fine block).  Only
+ * the sampling of rho0 and phi changes; NN coupling only. */
+#define DK_GRID_VERTEX 0
+#define DK_GRID_CELL 1
+
 /* ---- problem statement (Sec. 2, Sec. 3, Sec. 7) ---- */
 typedef struct { double amp, kx, ky, phase; } dk_mode;
 
@@ -136,7 +144,7 @@ typedef struct {
     dk_field rho0;            /* initial mean-field profile; rho^0 = I_h rho0 on every level */
     uint64_t seed;            /* Philox key                                                 */
     int32_t coupling;         /* DK_COUPLING_NN (default) or DK_COUPLING_FOURIER           */
-    int32_t reserved;
+    int32_t grid;             /* DK_GRID_VERTEX (default) or DK_GRID_CELL                  */
 } dk_problem;
 
 /* ---- per-level moment sums ---- */

@@ -50,7 +50,7 @@ class _Obs(C.Structure):
 class _Problem(C.Structure):
     _fields_ = [("box", C.c_double), ("n0", C.c_int32), ("levels", C.c_int32), ("mu", C.c_double),
                 ("N", C.c_double), ("steps0", C.c_int32), ("flux", C.c_int32), ("n_obs", C.c_int32),
-                ("pad", C.c_int32), ("obs", C.POINTER(_Obs)), ("rho0", _Field), ("seed", C.c_uint64)]
+                ("cell_centred", C.c_int32), ("obs", C.POINTER(_Obs)), ("rho0", _Field), ("seed", C.c_uint64)]
 
 
 def _load(path):
@@ -64,6 +64,7 @@ def _load(path):
                                      C.POINTER(C.c_float)]
     L.dko_em_step.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_int, dp, dp, dp]
     L.dko_field_grid.argtypes = [C.POINTER(_Field), C.c_double, C.c_int, dp]
+    L.dko_field_grid_at.argtypes = [C.POINTER(_Field), C.c_double, C.c_int, C.c_double, dp]
     L.dko_meanfield.argtypes = [C.POINTER(_Problem), C.c_int, dp, dp]
     L.dko_run_single.argtypes = [C.POINTER(_Problem), C.c_int, C.c_uint64, C.c_uint32, dp, dp, dp]
     L.dko_run_pair.argtypes = [C.POINTER(_Problem), C.c_int, C.c_uint64, C.c_uint32, dp, dp, dp,
@@ -115,7 +116,8 @@ class OracleProblem:
         for i, o in enumerate(p.obs):
             obs[i] = _Obs(_field(o.phi, self._keep), int(o.centre), int(o.scale_sqrtN), int(o.psi), 0)
         self._keep.append(obs)
-        self.c = _Problem(p.box, p.n0, p.levels, p.mu, p.N, p.steps(0), p.flux, len(p.obs), 0,
+        assert p.coupling == W.COUPLING_NN, "the library oracle runs the NN coupling; see oracle.fourier"
+        self.c = _Problem(p.box, p.n0, p.levels, p.mu, p.N, p.steps(0), p.flux, len(p.obs), int(p.grid == W.GRID_CELL),
                           C.cast(obs, C.POINTER(_Obs)), _field(p.rho0, self._keep), p.seed)
         self._centres = {}
 
@@ -183,11 +185,12 @@ def em_step(rho: np.ndarray, dbeta: np.ndarray, h: float, tau: float, N: float, 
     return out
 
 
-def field_grid(f: W.Field, box: float, n: int) -> np.ndarray:
+def field_grid(f: W.Field, box: float, n: int, offset: float = 0.0) -> np.ndarray:
+    """I_h f at the points ((i + offset) h, (j + offset) h), shape [y, x]."""
     keep = []
     cf = _field(f, keep)
     out = np.zeros(n * n)
-    lib().dko_field_grid(C.byref(cf), box, n, _dp(out))
+    lib().dko_field_grid_at(C.byref(cf), box, n, offset, _dp(out))
     return out.reshape(n, n)
 
 

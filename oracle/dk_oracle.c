@@ -183,7 +183,7 @@ typedef struct {
     int32_t steps0;       /* number of steps on level 0 (M_l = steps0 * 4^l) */
     int32_t flux;         /* 0 central, 1 staggered */
     int32_t n_obs;
-    int32_t pad;
+    int32_t cell_centred; /* 0: grid points x_i = i h; 1: cell centres x_i = (i + 1/2) h */
     const dko_obs* obs;
     dko_field rho0;
     uint64_t seed;
@@ -229,13 +229,26 @@ double dko_field_at(const dko_field* f, double box, double x, double y)
     }
 }
 
-/* I_h f on the n x n grid, x_i = i h, stored x fastest: out[x + n*y] */
-void dko_field_grid(const dko_field* f, double box, int n, double* out)
+/* I_h f on the n x n grid with points x_i = (i + offset) h, stored x fastest: out[x + n*y] */
+void dko_field_grid_at(const dko_field* f, double box, int n, double offset, double* out)
 {
     double h = box / n;
     for (int iy = 0; iy < n; ++iy)
         for (int ix = 0; ix < n; ++ix)
-            out[ix + n * iy] = dko_field_at(f, box, ix * h, iy * h);
+            out[ix + n * iy] = dko_field_at(f, box, (ix + offset) * h, (iy + offset) * h);
+}
+
+/* I_h f on the vertex grid x_i = i h */
+void dko_field_grid(const dko_field* f, double box, int n, double* out)
+{
+    dko_field_grid_at(f, box, n, 0.0, out);
+}
+
+/* I_h f on the problem's grid: vertices, or the cell centres of the symmetric NN coupling
+   (the remark after Sec. 3.2: the coupling unchanged on the points -pi + h/2, ..., pi - h/2) */
+static void problem_field(const dko_problem* p, const dko_field* f, int n, double* out)
+{
+    dko_field_grid_at(f, p->box, n, p->cell_centred ? 0.5 : 0.0, out);
 }
 
 /* ------------------------------------------------------------------------------------ */
@@ -362,13 +375,13 @@ void dko_meanfield(const dko_problem* p, int level, double* c_out, double* rho_o
     double* nxt = (double*)malloc(sizeof(double) * n * n);
     double* zero = (double*)calloc(2 * n * n, sizeof(double));
     double* phi = (double*)malloc(sizeof(double) * n * n);
-    dko_field_grid(&p->rho0, p->box, n, rho);
+    problem_field(p, &p->rho0, n, rho);
     for (long m = 0; m < M; ++m) {
         dko_em_step(n, h, tau, 1.0, 0, rho, zero, nxt);   /* dbeta = 0: no noise term */
         double* t = rho; rho = nxt; nxt = t;
     }
     for (int j = 0; j < p->n_obs; ++j) {
-        dko_field_grid(&p->obs[j].phi, p->box, n, phi);
+        problem_field(p, &p->obs[j].phi, n, phi);
         c_out[j] = inner_h(n, h, rho, phi);
     }
     if (rho_out) memcpy(rho_out, rho, sizeof(double) * n * n);
@@ -382,7 +395,7 @@ static void observables(const dko_problem* p, int n, double h, const double* rho
     double* phi = (double*)malloc(sizeof(double) * n * n);
     for (int j = 0; j < p->n_obs; ++j) {
         const dko_obs* o = &p->obs[j];
-        dko_field_grid(&o->phi, p->box, n, phi);
+        problem_field(p, &o->phi, n, phi);
         double L = inner_h(n, h, rho, phi);
         double X = L - (o->centre ? centre[j] : 0.0);
         if (o->scale_sqrtN) X *= sqrt(p->N);
@@ -405,7 +418,7 @@ void dko_run_single(const dko_problem* p, int level, uint64_t sample, uint32_t t
     double* nxt = (double*)malloc(sizeof(double) * n * n);
     double* z = (double*)malloc(sizeof(double) * 2 * n * n);
     double* db = (double*)malloc(sizeof(double) * 2 * n * n);
-    dko_field_grid(&p->rho0, p->box, n, rho);
+    problem_field(p, &p->rho0, n, rho);
     double st = sqrt(tau);
     for (long m = 0; m < M; ++m) {
         dko_noise_step(p->seed, tag, level, sample, n, (int)m, z);
@@ -442,8 +455,8 @@ void dko_run_pair(const dko_problem* p, int level, uint64_t sample, uint32_t tag
     double* z = (double*)malloc(sizeof(double) * 2 * nf * nf);
     double* dbf = (double*)malloc(sizeof(double) * 2 * nf * nf);
     double* dbc = (double*)malloc(sizeof(double) * 2 * nc * nc);
-    dko_field_grid(&p->rho0, p->box, nf, rf);
-    dko_field_grid(&p->rho0, p->box, nc, rc);
+    problem_field(p, &p->rho0, nf, rf);
+    problem_field(p, &p->rho0, nc, rc);
     double stf = sqrt(tf);
     for (long mc = 0; mc < Mc; ++mc) {
         memset(dbc, 0, sizeof(double) * 2 * nc * nc);

@@ -64,6 +64,10 @@ def coarse_increment(dbeta_sum: np.ndarray, box: float, nf: int, nc: int) -> np.
     return out
 
 
+def _vertex(p: W.Problem):
+    assert p.grid == W.GRID_VERTEX, "the Fourier coupling is set up on the vertex grid"
+
+
 def _observables(p: W.Problem, rho: np.ndarray, n: int, centre: np.ndarray) -> np.ndarray:
     """P_j = psi_j(s_j ((rho, I_h phi_j)_h - c_j)) of eq. (eqn_MLMCLevels)."""
     h2 = (p.box / n) ** 2
@@ -77,6 +81,7 @@ def _observables(p: W.Problem, rho: np.ndarray, n: int, centre: np.ndarray) -> n
 
 def centre(p: W.Problem, level: int) -> np.ndarray:
     """c_{l,j} = (rho_bar_l^M, I_h phi_j)_h: the noise-free scheme run to the final time."""
+    _vertex(p)
     n, h, tau = p.n(level), p.h(level), p.tau(level)
     rho = field_grid(p.rho0, p.box, n)
     zero = np.zeros((n, n, 2))
@@ -87,6 +92,7 @@ def centre(p: W.Problem, level: int) -> np.ndarray:
 
 def run_single(p: W.Problem, level: int, sample: int, tag: int = W.TAG_MLMC, c: np.ndarray | None = None):
     """(P_j) of one uncoupled path on level `level` (level 0 of the estimator, or plain MC)."""
+    _vertex(p)
     n, h, tau = p.n(level), p.h(level), p.tau(level)
     c = centre(p, level) if c is None else c
     rho = field_grid(p.rho0, p.box, n)
@@ -101,6 +107,7 @@ def run_pair(p: W.Problem, level: int, sample: int, tag: int = W.TAG_MLMC, cf: n
              cc: np.ndarray | None = None, want_field: bool = False):
     """(P_j^fine, P_j^coarse) of one Fourier-coupled pair (fine level `level`)."""
     assert p.coupling == W.COUPLING_FOURIER and level >= 1
+    _vertex(p)
     nf, nc = p.n(level), p.n(level - 1)
     hf, hc = p.h(level), p.h(level - 1)
     tf, tc = p.tau(level), p.tau(level - 1)

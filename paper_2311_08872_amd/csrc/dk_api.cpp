@@ -91,6 +91,7 @@ uint64_t problem_hash(const dk_problem* p)
     Hasher H;
     H.val(p->d); H.val(p->n0); H.val(p->levels); H.val(p->steps_policy); H.val(p->box); H.val(p->mu);
     H.val(p->T); H.val(p->N); H.val(p->flux); H.val(p->precision); H.val(p->n_obs); H.val(p->coupling);
+    H.val(p->grid);
     H.field(p->rho0);
     for (int j = 0; j < p->n_obs; ++j) {
         H.field(p->obs[j].phi); H.val(p->obs[j].centre); H.val(p->obs[j].scale_sqrtN); H.val(p->obs[j].psi);
@@ -160,6 +161,9 @@ int validate(const dk_problem* p)
     }
     if (p->coupling != DK_COUPLING_NN && p->coupling != DK_COUPLING_FOURIER)
         return fail(DK_EINVAL, "unknown coupling %d", p->coupling);
+    if (p->grid != DK_GRID_VERTEX && p->grid != DK_GRID_CELL) return fail(DK_EINVAL, "unknown grid %d", p->grid);
+    if (fourier(p) && p->grid != DK_GRID_VERTEX)
+        return fail(DK_EUNSUPPORTED, "the Fourier coupling is set up on the vertex grid");
     if (fourier(p)) {
         if (p->flux != DK_FLUX_CENTRAL) return fail(DK_EUNSUPPORTED, "the Fourier coupling runs the central flux only");
         if (p->levels > 6) return fail(DK_EINVAL, "levels = %d: the Fourier hierarchy has at most 6 levels", p->levels);
@@ -186,6 +190,23 @@ dk::FieldDev to_dev(const dk_field& f)
     for (int k = 0; k < f.n_modes; ++k) {
         d.amp[k] = f.modes[k].amp; d.kx[k] = f.modes[k].kx; d.ky[k] = f.modes[k].ky; d.phase[k] = f.modes[k].phase;
     }
+    return d;
+}
+
+// I_h f on the problem's grid for an n x n level: on cell centres the field is sampled at
+// (i + 1/2) h, which for every field kind is the same field with shifted parameters (a phase
+// for cosine modes, the centre for the bump and the sin^2 datum) sampled at i h.
+dk::FieldDev to_dev_on(const dk_problem* p, const dk_field& f, int n)
+{
+    dk::FieldDev d = to_dev(f);
+    if (p->grid != DK_GRID_CELL) return d;
+    const double delta = 0.5 * p->box / n;
+    const double two_pi = 6.28318530717958647692;
+    for (int k = 0; k < d.n_modes; ++k) d.phase[k] += two_pi * (d.kx[k] + d.ky[k]) * delta / p->box;
+    d.bump_cx -= delta;
+    d.bump_cy -= delta;
+    d.es_x0 -= delta;
+    d.es_y0 -= delta;
     return d;
 }
 
@@ -298,7 +319,7 @@ int compute_centre(dk_context* ctx, const dk_problem* p, int level, LevelTables&
         DevBuf r0;
         int rc = r0.ensure(sizeof(double) * n * n);
         if (rc) return rc;
-        HIP_TRY(dk::launch_field_eval(to_dev(p->rho0), p->box, n, r0.p, true, s));
+        HIP_TRY(dk::launch_field_eval(to_dev_on(p, p->rho0, n), p->box, n, r0.p, true, s));
         rc = ctx->per_sample.ensure(sizeof(double) * 2 * nobs);
         if (rc) return rc;
         std::vector<double> obs_host(3 * nobs);
@@ -326,7 +347,7 @@ int compute_centre(dk_context* ctx, const dk_problem* p, int level, LevelTables&
         if (rc) return rc;
         rc = ctx->scratch_c.ensure(sizeof(double) * nobs);
         if (rc) return rc;
-        HIP_TRY(dk::launch_field_eval(to_dev(p->rho0), p->box, n, ctx->mf0.p, true, s));
+        HIP_TRY(dk::launch_field_eval(to_dev_on(p, p->rho0, n), p->box, n, ctx->mf0.p, true, s));
         double* res = nullptr;
         HIP_TRY(dk::launch_meanfield_stream(n, a, (int)T.steps, (double*)ctx->mf0.p, (double*)ctx->mf1.p, &res, s));
         HIP_TRY(dk::launch_inner_products(res, n, (const double*)T.phi.p, nobs, T.h * T.h, (double*)ctx->scratch_c.p, s));
@@ -358,11 +379,11 @@ int ensure_level(dk_context* ctx, const dk_problem* p, int level, LevelTables** 
     const int nobs = p->n_obs;
     int rc = T->rho0.ensure((f64 ? 8 : 4) * (size_t)n * n);
     if (rc) return rc;
-    HIP_TRY(dk::launch_field_eval(to_dev(p->rho0), p->box, n, T->rho0.p, f64, s));
+    HIP_TRY(dk::launch_field_eval(to_dev_on(p, p->rho0, n), p->box, n, T->rho0.p, f64, s));
     rc = T->phi.ensure(sizeof(double) * (size_t)nobs * n * n);
     if (rc) return rc;
     for (int j = 0; j < nobs; ++j)
-        HIP_TRY(dk::launch_field_eval(to_dev(p->obs[j].phi), p->box, n, (double*)T->phi.p + (size_t)j * n * n, true, s));
+        HIP_TRY(dk::launch_field_eval(to_dev_on(p, p->obs[j].phi, n), p->box, n, (double*)T->phi.p + (size_t)j * n * n, true, s));
     bool any_centre = false;
     for (int j = 0; j < nobs; ++j) any_centre |= p->obs[j].centre != 0;
     if (any_centre) {

@@ -27,14 +27,14 @@ import numpy as np
 import dk_workloads as W
 
 
-def grid(n: int, box: float):
-    x = np.arange(n) * (box / n)
+def grid(n: int, box: float, offset: float = 0.0):
+    x = (np.arange(n) + offset) * (box / n)
     X, Y = np.meshgrid(x, x)      # arrays indexed [y, x]
     return X, Y
 
 
-def field_np(f: W.Field, box: float, n: int) -> np.ndarray:
-    X, Y = grid(n, box)
+def field_np(f: W.Field, box: float, n: int, offset: float = 0.0) -> np.ndarray:
+    X, Y = grid(n, box, offset)
     v = np.full((n, n), f.c0, dtype=np.float64)
     if f.kind in (W.FIELD_MODES, W.FIELD_CLIPPED):
         for m in f.modes:
@@ -90,8 +90,8 @@ def mobility(rho: np.ndarray, flux: int):
 
 def linear_mean(p: W.Problem, level: int, phi: W.Field) -> float:
     n, h = p.n(level), p.h(level)
-    rho0 = field_np(p.rho0, p.box, n)
-    return float(h * h * np.sum(A_pow(rho0, p.steps(level), p.mu) * field_np(phi, p.box, n)))
+    rho0 = field_np(p.rho0, p.box, n, p.offset)
+    return float(h * h * np.sum(A_pow(rho0, p.steps(level), p.mu) * field_np(phi, p.box, n, p.offset)))
 
 
 def fluct_second_moment(p: W.Problem, level: int, phi: W.Field, flux: int | None = None) -> float:
@@ -100,8 +100,8 @@ def fluct_second_moment(p: W.Problem, level: int, phi: W.Field, flux: int | None
     flux = p.flux if flux is None else flux
     n, h, tau, M = p.n(level), p.h(level), p.tau(level), p.steps(level)
     lam = heat_multiplier(n, p.mu)
-    r0 = np.fft.fft2(field_np(p.rho0, p.box, n))
-    f0 = np.fft.fft2(field_np(phi, p.box, n))
+    r0 = np.fft.fft2(field_np(p.rho0, p.box, n, p.offset))
+    f0 = np.fft.fft2(field_np(phi, p.box, n, p.offset))
     S = 0.0
     for m in range(M):
         rho = np.real(np.fft.ifft2(r0 * lam ** m))
@@ -124,10 +124,10 @@ def pair_variance_linear(p: W.Problem, level: int, phi: W.Field, flux: int | Non
     Mf = p.steps(level)
     Mc = Mf // 4
     lamf, lamc = heat_multiplier(nf, p.mu), heat_multiplier(nc, p.mu)
-    rf0 = np.fft.fft2(field_np(p.rho0, p.box, nf))
-    rc0 = np.fft.fft2(field_np(p.rho0, p.box, nc))
-    ff0 = np.fft.fft2(field_np(phi, p.box, nf))
-    fc0 = np.fft.fft2(field_np(phi, p.box, nc))
+    rf0 = np.fft.fft2(field_np(p.rho0, p.box, nf, p.offset))
+    rc0 = np.fft.fft2(field_np(p.rho0, p.box, nc, p.offset))
+    ff0 = np.fft.fft2(field_np(phi, p.box, nf, p.offset))
+    fc0 = np.fft.fft2(field_np(phi, p.box, nc, p.offset))
     V = 0.0
     coarse_cache = {}
     for m in range(Mf):
@@ -180,10 +180,10 @@ def pair_variance_linear_fourier(p: W.Problem, level: int, phi: W.Field) -> floa
     Mc = Mf // 9
     K = restriction_1d(nf, nc)
     lamf, lamc = heat_multiplier(nf, p.mu), heat_multiplier(nc, p.mu)
-    rf0 = np.fft.fft2(field_np(p.rho0, p.box, nf))
-    rc0 = np.fft.fft2(field_np(p.rho0, p.box, nc))
-    ff0 = np.fft.fft2(field_np(phi, p.box, nf))
-    fc0 = np.fft.fft2(field_np(phi, p.box, nc))
+    rf0 = np.fft.fft2(field_np(p.rho0, p.box, nf, p.offset))
+    rc0 = np.fft.fft2(field_np(p.rho0, p.box, nc, p.offset))
+    ff0 = np.fft.fft2(field_np(phi, p.box, nf, p.offset))
+    fc0 = np.fft.fft2(field_np(phi, p.box, nc, p.offset))
     V = 0.0
     lifted = None
     for m in range(Mf):
@@ -209,7 +209,7 @@ def one_step_sigma2(p: W.Problem, level: int, phi: W.Field, flux: int | None = N
     """Variance of X after exactly one step from a deterministic rho0: tau (rho0^+, |grad phi|^2)_h."""
     flux = p.flux if flux is None else flux
     n, h, tau = p.n(level), p.h(level), p.tau(level)
-    rho0 = field_np(p.rho0, p.box, n)
-    gx, gy = grad(field_np(phi, p.box, n), h, flux)
+    rho0 = field_np(p.rho0, p.box, n, p.offset)
+    gx, gy = grad(field_np(phi, p.box, n, p.offset), h, flux)
     mx, my = mobility(rho0, flux)
     return tau * h * h * float(np.sum(mx * gx * gx + my * gy * gy))
