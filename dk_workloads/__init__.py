@@ -104,6 +104,7 @@ class Problem:
     seed: int = 0
     coupling: int = COUPLING_NN
     grid: int = GRID_VERTEX
+    b0: float = 0.0             # implicit weight of eq. (FullyDiscreteDK), b1 = 1 - b0 (0: explicit EM)
 
     # --- derived level data (pure bookkeeping, no method arithmetic) ---
     @property

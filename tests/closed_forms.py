@@ -3,9 +3,10 @@
 These are consequences of the paper's statements, computed in Fourier space, and serve as
 pins for the oracle (they share no code with it):
 
-* the noise-free scheme is rho^{m+1} = A rho^m with A = I + (tau/2) Lap_h, whose Fourier
-  multiplier is g_k = 1 - 2 mu (sin^2(pi k1/n) + sin^2(pi k2/n)) (Appendix A, operator A_h
-  with b0 = 0, b1 = 1);
+* the noise-free scheme is rho^{m+1} = A rho^m with A = (I - tau b0/2 Lap_h)^{-1}(I + tau b1/2
+  Lap_h) (Appendix A), whose Fourier multiplier is g_k = (1 - 2 b1 mu s_k)/(1 + 2 b0 mu s_k),
+  s_k = sin^2(pi k1/n) + sin^2(pi k2/n) (b0 = 0, b1 = 1 is the explicit scheme of Sec. 7); the
+  noise increment passes through (I - tau b0/2 Lap_h)^{-1} as well;
 * Lemma "lem_Discrete_Martingale": (rho^m, A^{M-m} phi)_h is a martingale, hence
   E<rho^M, phi>_h = <A^M rho^0, phi>_h for every N (the noise increments have mean 0);
 * the martingale increments are orthogonal, which gives
@@ -55,14 +56,24 @@ def field_np(f: W.Field, box: float, n: int, offset: float = 0.0) -> np.ndarray:
     raise ValueError(f.kind)
 
 
-def heat_multiplier(n: int, mu: float) -> np.ndarray:
+def heat_multiplier(n: int, mu: float, b0: float = 0.0) -> np.ndarray:
+    """Fourier multiplier of the noise-free step A_h = (I - tau b0/2 Lap_h)^{-1} (I + tau b1/2 Lap_h)
+    (Appendix A), b1 = 1 - b0: (1 - 2 b1 mu s) / (1 + 2 b0 mu s), s = sin^2(pi k1/n) + sin^2(pi k2/n)."""
     k = np.arange(n)
     s = np.sin(math.pi * k / n) ** 2
-    return 1.0 - 2.0 * mu * (s[None, :] + s[:, None])
+    ss = s[None, :] + s[:, None]
+    return (1.0 - 2.0 * (1.0 - b0) * mu * ss) / (1.0 + 2.0 * b0 * mu * ss)
 
 
-def A_pow(f: np.ndarray, m: int, mu: float) -> np.ndarray:
-    lam = heat_multiplier(f.shape[0], mu)
+def solve_multiplier(n: int, mu: float, b0: float) -> np.ndarray:
+    """Multiplier of (I - tau b0/2 Lap_h)^{-1}, which the noise increment also passes through."""
+    k = np.arange(n)
+    s = np.sin(math.pi * k / n) ** 2
+    return 1.0 / (1.0 + 2.0 * b0 * mu * (s[None, :] + s[:, None]))
+
+
+def A_pow(f: np.ndarray, m: int, mu: float, b0: float = 0.0) -> np.ndarray:
+    lam = heat_multiplier(f.shape[0], mu, b0)
     return np.real(np.fft.ifft2(np.fft.fft2(f) * lam ** m))
 
 
@@ -91,7 +102,7 @@ def mobility(rho: np.ndarray, flux: int):
 def linear_mean(p: W.Problem, level: int, phi: W.Field) -> float:
     n, h = p.n(level), p.h(level)
     rho0 = field_np(p.rho0, p.box, n, p.offset)
-    return float(h * h * np.sum(A_pow(rho0, p.steps(level), p.mu) * field_np(phi, p.box, n, p.offset)))
+    return float(h * h * np.sum(A_pow(rho0, p.steps(level), p.mu, p.b0) * field_np(phi, p.box, n, p.offset)))
 
 
 def fluct_second_moment(p: W.Problem, level: int, phi: W.Field, flux: int | None = None) -> float:
@@ -99,13 +110,14 @@ def fluct_second_moment(p: W.Problem, level: int, phi: W.Field, flux: int | None
     sqrt(N)-scaled linear observable in the high-density limit (exact lower bound)."""
     flux = p.flux if flux is None else flux
     n, h, tau, M = p.n(level), p.h(level), p.tau(level), p.steps(level)
-    lam = heat_multiplier(n, p.mu)
+    lam = heat_multiplier(n, p.mu, p.b0)
+    sol = solve_multiplier(n, p.mu, p.b0)
     r0 = np.fft.fft2(field_np(p.rho0, p.box, n, p.offset))
     f0 = np.fft.fft2(field_np(phi, p.box, n, p.offset))
     S = 0.0
     for m in range(M):
         rho = np.real(np.fft.ifft2(r0 * lam ** m))
-        ph = np.real(np.fft.ifft2(f0 * lam ** (M - m - 1)))
+        ph = np.real(np.fft.ifft2(f0 * sol * lam ** (M - m - 1)))
         gx, gy = grad(ph, h, flux)
         mx, my = mobility(rho, flux)
         S += tau * h * h * float(np.sum(mx * gx * gx + my * gy * gy))
@@ -123,7 +135,8 @@ def pair_variance_linear(p: W.Problem, level: int, phi: W.Field, flux: int | Non
     tf = p.tau(level)
     Mf = p.steps(level)
     Mc = Mf // 4
-    lamf, lamc = heat_multiplier(nf, p.mu), heat_multiplier(nc, p.mu)
+    lamf, lamc = heat_multiplier(nf, p.mu, p.b0), heat_multiplier(nc, p.mu, p.b0)
+    solf, solc = solve_multiplier(nf, p.mu, p.b0), solve_multiplier(nc, p.mu, p.b0)
     rf0 = np.fft.fft2(field_np(p.rho0, p.box, nf, p.offset))
     rc0 = np.fft.fft2(field_np(p.rho0, p.box, nc, p.offset))
     ff0 = np.fft.fft2(field_np(phi, p.box, nf, p.offset))
@@ -134,7 +147,7 @@ def pair_variance_linear(p: W.Problem, level: int, phi: W.Field, flux: int | Non
         mc = m // 4
         if mc not in coarse_cache:
             rc = np.real(np.fft.ifft2(rc0 * lamc ** mc))
-            phc = np.real(np.fft.ifft2(fc0 * lamc ** (Mc - mc - 1)))
+            phc = np.real(np.fft.ifft2(fc0 * solc * lamc ** (Mc - mc - 1)))
             gcx, gcy = grad(phc, hc, flux)
             mcx, mcy = mobility(rc, flux)
             ax = np.sqrt(mcx) * gcx
@@ -143,7 +156,7 @@ def pair_variance_linear(p: W.Problem, level: int, phi: W.Field, flux: int | Non
             coarse_cache = {mc: (np.kron(ax, np.ones((2, 2))), np.kron(ay, np.ones((2, 2))))}
         cx, cy = coarse_cache[mc]
         rf = np.real(np.fft.ifft2(rf0 * lamf ** m))
-        phf = np.real(np.fft.ifft2(ff0 * lamf ** (Mf - m - 1)))
+        phf = np.real(np.fft.ifft2(ff0 * solf * lamf ** (Mf - m - 1)))
         gfx, gfy = grad(phf, hf, flux)
         mfx, mfy = mobility(rf, flux)
         dx = np.sqrt(mfx) * gfx - cx
