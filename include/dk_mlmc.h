@@ -5,7 +5,8 @@
  * equation from Fluctuating Hydrodynamics" (arXiv 2311.08872).
  *
  *   discrete model     Definition "def_discrete_DK", eq. (FullyDiscreteDK), explicit
- *                      Euler--Maruyama (b0 = 0, b1 = 1, Sec. 7), V = 0, d = 2
+ *                      Euler--Maruyama (b0 = 0, b1 = 1, Sec. 7) or any b0 in (0, 1]
+ *                      (dk_problem.b0), V = 0, d = 2
  *   operators          5-point Laplacian and central divergence (Sec. 7, "Differential
  *                      operators"); DK_FLUX_STAGGERED selects a forward difference of edge
  *                      fluxes with the edge-averaged density under the square root
@@ -145,6 +146,12 @@ typedef struct {
     uint64_t seed;            /* Philox key                                                 */
     int32_t coupling;         /* DK_COUPLING_NN (default) or DK_COUPLING_FOURIER           */
     int32_t grid;             /* DK_GRID_VERTEX (default) or DK_GRID_CELL                  */
+    double b0;                /* implicit weight of eq. (FullyDiscreteDK), b1 = 1 - b0, in
+                                 [0, 1]; 0 (default) is the explicit scheme of Sec. 7.  b0 > 0:
+                                 NN coupling, central flux, grids up to 64 x 64, stable for
+                                 mu (1 - 2 b0) <= 1/2 (any mu once b0 >= 1/2); each step
+                                 filters the explicit increment with (I - tau b0/2 Lap_h)^{-1}
+                                 by an FFT per step and grid (Appendix A, operator A_h)     */
 } dk_problem;
 
 /* ---- per-level moment sums ---- */

@@ -60,7 +60,7 @@ class CProblem:
         self._keep.append(obs)
         self.c = L.dk_problem(2, p.n0, p.levels, p.steps_policy, p.box, p.mu, p.T, p.N, p.flux, p.precision,
                               len(p.obs), p.primary, C.cast(obs, C.POINTER(L.dk_obs)), _field(p.rho0, self._keep),
-                              p.seed, p.coupling, p.grid)
+                              p.seed, p.coupling, p.grid, float(p.b0))
 
     @property
     def ref(self):

@@ -35,7 +35,7 @@ class dk_problem(C.Structure):
                 ("box", C.c_double), ("mu", C.c_double), ("T", C.c_double), ("N", C.c_double),
                 ("flux", C.c_int32), ("precision", C.c_int32), ("n_obs", C.c_int32), ("primary_obs", C.c_int32),
                 ("obs", C.POINTER(dk_obs)), ("rho0", dk_field), ("seed", C.c_uint64),
-                ("coupling", C.c_int32), ("grid", C.c_int32)]
+                ("coupling", C.c_int32), ("grid", C.c_int32), ("b0", C.c_double)]
 
 
 class dk_moments(C.Structure):

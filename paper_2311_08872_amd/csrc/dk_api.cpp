@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -17,6 +18,7 @@
 
 #include "dk_cnn.h"
 #include "dk_fourier.h"
+#include "dk_theta.h"
 #include "dk_internal.h"
 #include "dk_round.h"
 #include "dk_stream.h"
@@ -91,7 +93,7 @@ uint64_t problem_hash(const dk_problem* p)
     Hasher H;
     H.val(p->d); H.val(p->n0); H.val(p->levels); H.val(p->steps_policy); H.val(p->box); H.val(p->mu);
     H.val(p->T); H.val(p->N); H.val(p->flux); H.val(p->precision); H.val(p->n_obs); H.val(p->coupling);
-    H.val(p->grid);
+    H.val(p->grid); H.val(p->b0);
     H.field(p->rho0);
     for (int j = 0; j < p->n_obs; ++j) {
         H.field(p->obs[j].phi); H.val(p->obs[j].centre); H.val(p->obs[j].scale_sqrtN); H.val(p->obs[j].psi);
@@ -123,6 +125,7 @@ long steps0_of(const dk_problem* p)
 }
 
 bool fourier(const dk_problem* p) { return p->coupling == DK_COUPLING_FOURIER; }
+bool implicit(const dk_problem* p) { return p->b0 > 0.0; }
 // h_{l-1} / h_l: 2 (NN coupling) or 3 (Fourier coupling)
 int level_ratio(const dk_problem* p) { return fourier(p) ? 3 : 2; }
 long ipow(long b, int e)
@@ -143,7 +146,10 @@ int validate(const dk_problem* p)
     if (p->n0 < 4 || (p->n0 & 1)) return fail(DK_EINVAL, "n0 = %d must be even and >= 4", p->n0);
     if (p->levels < 1 || p->levels > DK_MAX_LEVELS) return fail(DK_EINVAL, "levels = %d outside [1, %d]", p->levels, DK_MAX_LEVELS);
     if (!(p->box > 0)) return fail(DK_EINVAL, "box must be > 0");
-    if (!(p->mu > 0) || p->mu > 0.5 + 1e-12) return fail(DK_EINVAL, "mu = %g outside (0, 1/d]: the explicit scheme is unstable", p->mu);
+    if (!(p->b0 >= 0.0 && p->b0 <= 1.0)) return fail(DK_EINVAL, "b0 = %g outside [0, 1]", p->b0);
+    // |(1 - 2 b1 mu s)/(1 + 2 b0 mu s)| <= 1 for s in [0, 2]: mu (1 - 2 b0) <= 1/2
+    if (!(p->mu > 0) || p->mu * (1.0 - 2.0 * p->b0) > 0.5 + 1e-12)
+        return fail(DK_EINVAL, "mu = %g with b0 = %g: the scheme is unstable (mu (1 - 2 b0) must be <= 1/d)", p->mu, p->b0);
     if (!(p->T > 0)) return fail(DK_EINVAL, "T must be > 0");
     if (!(p->N > 0)) return fail(DK_EINVAL, "N must be > 0");
     if (p->flux != DK_FLUX_CENTRAL && p->flux != DK_FLUX_STAGGERED) return fail(DK_EINVAL, "unknown flux %d", p->flux);
@@ -164,6 +170,14 @@ int validate(const dk_problem* p)
     if (p->grid != DK_GRID_VERTEX && p->grid != DK_GRID_CELL) return fail(DK_EINVAL, "unknown grid %d", p->grid);
     if (fourier(p) && p->grid != DK_GRID_VERTEX)
         return fail(DK_EUNSUPPORTED, "the Fourier coupling is set up on the vertex grid");
+    if (implicit(p)) {
+        if (fourier(p)) return fail(DK_EUNSUPPORTED, "b0 > 0 runs with the NN coupling");
+        if (p->flux != DK_FLUX_CENTRAL) return fail(DK_EUNSUPPORTED, "b0 > 0 runs the central flux only");
+        for (int l = 0; l < p->levels; ++l)
+            if (!dk::theta_supported(p->n0 << l, l >= 1))
+                return fail(DK_EUNSUPPORTED, "b0 > 0: no kernel for the %d x %d grid of level %d (powers of two up to 64)",
+                            p->n0 << l, p->n0 << l, l);
+    }
     if (fourier(p)) {
         if (p->flux != DK_FLUX_CENTRAL) return fail(DK_EUNSUPPORTED, "the Fourier coupling runs the central flux only");
         if (p->levels > 6) return fail(DK_EINVAL, "levels = %d: the Fourier hierarchy has at most 6 levels", p->levels);
@@ -237,6 +251,7 @@ struct LevelTables {
     DevBuf rbar;                  // FP64 discrete mean field at the final time [n*n]
     bool have_rbar = false;
     DevBuf fourier_K;             // Fourier pairs with this fine level: projection kernel [n/3][n], state type
+    DevBuf theta_tw, theta_sol;   // b0 > 0: twiddles exp(-2 pi i k/n) [n/2][2] and the solve multipliers [n][n]
 };
 
 struct ProblemTables {
@@ -308,12 +323,75 @@ double noise_coeff(const dk_problem* p, double h, double sigma)
 
 int ensure_level(dk_context* ctx, const dk_problem* p, int level, LevelTables** out, hipStream_t s);
 
+// Noise-free scheme with weight b0 to step M, in FP64 on the host: every Fourier mode is
+// multiplied by g^M, g = (1 - 2 b1 mu s)/(1 + 2 b0 mu s), s = sin^2(pi kx/n) + sin^2(pi ky/n)
+// (Appendix A, operator A_h); separable DFTs, n <= 64.
+void theta_meanfield_host(int n, double mu, double b0, long M, std::vector<double>& rho)
+{
+    typedef std::complex<double> cd;
+    const double pi = 3.14159265358979323846;
+    std::vector<cd> W((size_t)n * n), X((size_t)n * n), Y((size_t)n * n);
+    for (int j = 0; j < n; ++j)
+        for (int k = 0; k < n; ++k) W[(size_t)j * n + k] = std::polar(1.0, -2.0 * pi * (double)((j * k) % n) / n);
+    // forward: Y = W rho W^T  (rho indexed [y][x])
+    for (int y = 0; y < n; ++y)
+        for (int kx = 0; kx < n; ++kx) {
+            cd acc = 0.0;
+            for (int x = 0; x < n; ++x) acc += W[(size_t)kx * n + x] * rho[(size_t)y * n + x];
+            X[(size_t)y * n + kx] = acc;
+        }
+    for (int ky = 0; ky < n; ++ky)
+        for (int kx = 0; kx < n; ++kx) {
+            cd acc = 0.0;
+            for (int y = 0; y < n; ++y) acc += W[(size_t)ky * n + y] * X[(size_t)y * n + kx];
+            const double sx = std::sin(pi * kx / n), sy = std::sin(pi * ky / n), ss = sx * sx + sy * sy;
+            const double g = (1.0 - 2.0 * (1.0 - b0) * mu * ss) / (1.0 + 2.0 * b0 * mu * ss);
+            Y[(size_t)ky * n + kx] = acc * std::pow(g, (double)M);
+        }
+    // inverse: conj(W) on both sides, 1/n^2
+    for (int y = 0; y < n; ++y)
+        for (int kx = 0; kx < n; ++kx) {
+            cd acc = 0.0;
+            for (int ky = 0; ky < n; ++ky) acc += std::conj(W[(size_t)y * n + ky]) * Y[(size_t)ky * n + kx];
+            X[(size_t)y * n + kx] = acc;
+        }
+    for (int y = 0; y < n; ++y)
+        for (int x = 0; x < n; ++x) {
+            cd acc = 0.0;
+            for (int kx = 0; kx < n; ++kx) acc += std::conj(W[(size_t)x * n + kx]) * X[(size_t)y * n + kx];
+            rho[(size_t)y * n + x] = acc.real() / ((double)n * n);
+        }
+}
+
 int compute_centre(dk_context* ctx, const dk_problem* p, int level, LevelTables& T, hipStream_t s, double* rho_out)
 {
     const int n = T.n;
     const int nobs = p->n_obs;
     std::vector<double> c(nobs, 0.0);
     const double a = 0.5 * p->mu;
+    if (implicit(p)) {
+        DevBuf r0;
+        int rc = r0.ensure(sizeof(double) * n * n);
+        if (rc) return rc;
+        HIP_TRY(dk::launch_field_eval(to_dev_on(p, p->rho0, n), p->box, n, r0.p, true, s));
+        std::vector<double> rho((size_t)n * n), phi((size_t)nobs * n * n);
+        HIP_TRY(hipMemcpyAsync(rho.data(), r0.p, sizeof(double) * n * n, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(phi.data(), T.phi.p, sizeof(double) * nobs * n * n, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        theta_meanfield_host(n, p->mu, p->b0, T.steps, rho);
+        for (int j = 0; j < nobs; ++j) {
+            double acc = 0.0;
+            for (size_t i = 0; i < (size_t)n * n; ++i) acc += rho[i] * phi[(size_t)j * n * n + i];
+            c[j] = T.h * T.h * acc;
+        }
+        if (rho_out) {
+            HIP_TRY(hipMemcpyAsync(rho_out, rho.data(), sizeof(double) * n * n, hipMemcpyHostToDevice, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+        T.centre = c;
+        T.have_centre = true;
+        return DK_OK;
+    }
     if (dk::level_supported(n)) {
         // FP64 rho0 for the noise-free resident kernel
         DevBuf r0;
@@ -822,6 +900,103 @@ int run_fourier(dk_context* ctx, const dk_problem* p, int level, bool pair, uint
     return DK_OK;
 }
 
+// Levels with b0 > 0: per-level tables (twiddles, solve multipliers), then chunks of samples
+// with blocks striding over each chunk, the moments in chunk order.
+int theta_tables(const dk_problem* p, LevelTables* T, hipStream_t s)
+{
+    if (T->theta_tw.p) return DK_OK;
+    const int n = T->n;
+    const bool f64 = p->precision == DK_PREC_F64;
+    const size_t esize = f64 ? 8 : 4;
+    const double pi = 3.14159265358979323846;
+    std::vector<double> tw(n), sol((size_t)n * n);
+    for (int k = 0; k < n / 2; ++k) {
+        tw[2 * k] = std::cos(2.0 * pi * k / n);
+        tw[2 * k + 1] = -std::sin(2.0 * pi * k / n);
+    }
+    for (int ky = 0; ky < n; ++ky)
+        for (int kx = 0; kx < n; ++kx) {
+            const double sx = std::sin(pi * kx / n), sy = std::sin(pi * ky / n);
+            sol[(size_t)ky * n + kx] = 1.0 / (1.0 + 2.0 * p->b0 * p->mu * (sx * sx + sy * sy));
+        }
+    int rc;
+    if ((rc = T->theta_tw.ensure(esize * tw.size())) || (rc = T->theta_sol.ensure(esize * sol.size()))) return rc;
+    std::vector<float> twf(tw.begin(), tw.end()), solf(sol.begin(), sol.end());
+    HIP_TRY(hipMemcpyAsync(T->theta_tw.p, f64 ? (const void*)tw.data() : (const void*)twf.data(), esize * tw.size(),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(T->theta_sol.p, f64 ? (const void*)sol.data() : (const void*)solf.data(), esize * sol.size(),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return DK_OK;
+}
+
+int run_theta(dk_context* ctx, const dk_problem* p, int level, bool pair, uint64_t first, uint64_t count,
+              const dk::LevelArgs& A, LevelTables* Tf, LevelTables* Tc, dk_moments* sums_out, double* per_sample_out,
+              hipStream_t s, double* cell_updates, uint64_t nchunks, uint64_t ch, size_t mom_stride)
+{
+    const int nf = A.nf, nobs = p->n_obs;
+    int rc;
+    if ((rc = theta_tables(p, Tf, s))) return rc;
+    if (pair && (rc = theta_tables(p, Tc, s))) return rc;
+    dk::ThetaArgs F{};
+    F.n = nf; F.level_id = level; F.tag = A.tag; F.seed = A.seed; F.steps = A.steps; F.n_obs = nobs;
+    F.a = A.a; F.kf = A.kf; F.kc = A.kc;
+    F.h2f = A.h2f; F.h2c = A.h2c;
+    F.rho0_f = A.rho0_f; F.rho0_c = A.rho0_c; F.phi_f = A.phi_f; F.phi_c = A.phi_c; F.obs_f = A.obs_f; F.obs_c = A.obs_c;
+    F.tw = Tf->theta_tw.p;
+    F.sol_f = Tf->theta_sol.p;
+    F.sol_c = pair ? Tc->theta_sol.p : nullptr;
+    while (ctx->ev_pool.size() < 2 * nchunks) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        ctx->ev_pool.push_back(e);
+    }
+    const bool log = std::getenv("DK_LOG") != nullptr;
+    for (uint64_t k = 0; k < nchunks; ++k) {
+        const uint64_t b = k * ch;
+        const uint64_t c = std::min(ch, count - b);
+        F.first = first + b;
+        F.count = c;
+        F.out = per_sample_out ? per_sample_out + b * nobs * 2 : (double*)ctx->per_sample.p;
+        HIP_TRY(hipEventRecord(ctx->ev_pool[2 * k], s));
+        HIP_TRY(dk::launch_theta(F, p->precision, pair, dk::theta_grid(nf, p->precision, c), s));
+        HIP_TRY(hipEventRecord(ctx->ev_pool[2 * k + 1], s));
+        HIP_TRY(dk::launch_moments(F.out, c, nobs, (double*)ctx->moments.p + k * mom_stride, s));
+        if (log && nchunks > 1) {
+            HIP_TRY(hipEventSynchronize(ctx->ev_pool[2 * k + 1]));
+            std::fprintf(stderr, "[dk] b0 = %g level %d%s launch %llu/%llu (%llu samples)\n", p->b0, level, pair ? " pair" : "",
+                         (unsigned long long)(k + 1), (unsigned long long)nchunks, (unsigned long long)c);
+            std::fflush(stderr);
+        }
+    }
+    ctx->host_mom.resize(mom_stride * nchunks);
+    HIP_TRY(hipMemcpyAsync(ctx->host_mom.data(), ctx->moments.p, sizeof(double) * mom_stride * nchunks,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const double per = (double)nf * nf * (double)A.steps * (pair ? pair_factor(p) : 1.0);
+    {
+        KStat& st = ctx->stats[std::make_pair(level, pair ? 1 : 0)];
+        for (uint64_t k = 0; k < nchunks; ++k) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, ctx->ev_pool[2 * k], ctx->ev_pool[2 * k + 1]));
+            st.ms += ms;
+        }
+        st.launches += nchunks;
+        st.samples += count;
+        st.rows = 0;   // b0 > 0 kernel: the state in LDS, no tile shapes
+        st.cells += per * (double)count;
+    }
+    for (uint64_t k = 0; k < nchunks; ++k) {
+        const uint64_t c = std::min(ch, count - k * ch);
+        for (int j = 0; j < nobs; ++j) merge_moments(sums_out[j], &ctx->host_mom[k * mom_stride + j * DK_NMOM * 2], c);
+    }
+    for (int j = 0; j < nobs; ++j)
+        for (int m = 0; m < DK_NMOM; ++m)
+            if (!std::isfinite(mom_value(sums_out[j], m))) return fail(DK_ENUMERIC, "non-finite sample values on level %d", level);
+    if (cell_updates) *cell_updates += per * (double)count;
+    return DK_OK;
+}
+
 // Run samples [first, first+count) of level `level` (coupled pair if `pair`), reduce the
 // per-sample values in chunk order and return per-observable moments.
 int run_level(dk_context* ctx, const dk_problem* p, int level, bool pair, uint64_t first, uint64_t count,
@@ -835,9 +1010,10 @@ int run_level(dk_context* ctx, const dk_problem* p, int level, bool pair, uint64
     if (count > 0 && first + count < first) return fail(DK_EINVAL, "sample range overflows");
     if (first + count > (1ull << 48)) return fail(DK_EINVAL, "sample index beyond 2^48");
     const int nf = level_n(p, level);
-    const bool four = fourier(p);
-    const bool stream = !four && (!dk::level_supported(nf) || (ctx->force_stream && dk::stream_supported(nf)));
+    const bool four = fourier(p), theta = implicit(p);
+    const bool stream = !four && !theta && (!dk::level_supported(nf) || (ctx->force_stream && dk::stream_supported(nf)));
     if (four && (field_f || field_c)) return fail(DK_EUNSUPPORTED, "field output is not available for the Fourier coupling");
+    if (theta && (field_f || field_c)) return fail(DK_EUNSUPPORTED, "field output is not available for b0 > 0");
     if (stream) {
         if (!dk::stream_supported(nf))
             return fail(DK_EUNSUPPORTED, "grid %d x %d: neither the resident nor the streaming kernel supports it", nf, nf);
@@ -892,6 +1068,9 @@ int run_level(dk_context* ctx, const dk_problem* p, int level, bool pair, uint64
     if (four)
         return run_fourier(ctx, p, level, pair, first, count, A, Tf, Tc, sums_out, per_sample_out, s, cell_updates, nchunks,
                            ch, mom_stride);
+    if (theta)
+        return run_theta(ctx, p, level, pair, first, count, A, Tf, Tc, sums_out, per_sample_out, s, cell_updates, nchunks,
+                         ch, mom_stride);
     int variant = 0;
     rc = choose_shape(ctx, p, pair, A, count, (double)nf * nf * (double)Tf->steps * (pair ? 1.0 + 1.0 / 16.0 : 1.0), s,
                       &variant);
@@ -958,7 +1137,7 @@ int run_level(dk_context* ctx, const dk_problem* p, int level, bool pair, uint64
 int level_args(dk_context* ctx, const dk_problem* p, int l, bool pair, uint32_t tag, hipStream_t s, dk::LevelArgs* out,
                double* cells_per_sample)
 {
-    if (fourier(p)) return fail(DK_EUNSUPPORTED, "the Fourier coupling runs level by level");
+    if (fourier(p) || implicit(p)) return fail(DK_EUNSUPPORTED, "the Fourier coupling and b0 > 0 run level by level");
     const int nf = level_n(p, l);
     LevelTables *Tf = nullptr, *Tc = nullptr;
     int rc = ensure_level(ctx, p, l, &Tf, s);
@@ -1121,7 +1300,7 @@ int run_round(dk_context* ctx, const dk_problem* p, int L, const uint64_t* first
 bool round_eligible(const dk_problem* p, int l, bool force_stream)
 {
     const int nf = level_n(p, l);
-    return !fourier(p) && p->precision == DK_PREC_F32 && p->n_obs <= dk::round_max_obs() && !force_stream &&
+    return !fourier(p) && !implicit(p) && p->precision == DK_PREC_F32 && p->n_obs <= dk::round_max_obs() && !force_stream &&
            dk::round_kind(nf, l >= 1) >= 0;
 }
 
@@ -1741,7 +1920,7 @@ int gpu_round(void* user, int L, const uint64_t* first, const uint64_t* count, d
         const int nf = level_n(G.p, l);
         const bool cv = l >= 1 && G.cv_params && ((G.cv_mask >> l) & 1u);
         const bool streamed = !fourier(G.p) && (!dk::level_supported(nf) || (G.ctx->force_stream && dk::stream_supported(nf)));
-        const bool outside = fourier(G.p) ||
+        const bool outside = fourier(G.p) || implicit(G.p) ||
                              (G.round_mode == 3 && G.p->precision == DK_PREC_F32 && !round_eligible(G.p, l, G.ctx->force_stream));
         if ((cv || streamed || outside || G.plain_mc) && count[l] > 0) {
             double s2[2] = {0, 0};
@@ -1867,7 +2046,7 @@ int dk_cv_train(dk_context* ctx, const dk_problem* problem, int32_t level, uint6
     if (level < 1 || level >= problem->levels) return fail(DK_EINVAL, "control variate needs 1 <= level < levels");
     if (epochs < 1 || batch < 1 || n_train < (uint64_t)batch) return fail(DK_EINVAL, "need epochs >= 1 and n_train >= batch >= 1");
     if (!(lr > 0)) return fail(DK_EINVAL, "lr must be > 0");
-    if (fourier(problem)) return fail(DK_EUNSUPPORTED, "the control variate is built for the NN coupling");
+    if (fourier(problem) || implicit(problem)) return fail(DK_EUNSUPPORTED, "the control variate is built for the explicit NN scheme");
     const int nc = problem->n0 << (level - 1);
     if (nc % 4) return fail(DK_EINVAL, "coarse grid must be a multiple of 4");
     HIP_TRY(hipSetDevice(ctx->device));
@@ -2280,7 +2459,7 @@ int dk_mlmc_estimate(dk_context* ctx, const dk_problem* problem, double eps, con
     G.tag = mc ? DK_TAG_MC : DK_TAG_MLMC;
     G.zmom.assign(problem->levels, dk_moments{});
     if (o.cv_params && !mc) {
-        if (fourier(problem)) return fail(DK_EUNSUPPORTED, "the control variate is built for the NN coupling");
+        if (fourier(problem) || implicit(problem)) return fail(DK_EUNSUPPORTED, "the control variate is built for the explicit NN scheme");
         G.cv_params = o.cv_params;
         G.cv_mask = o.cv_level_mask & ~1u;
         G.cv_ratio = o.cv_ratio > 0 ? o.cv_ratio : 4;
