@@ -68,14 +68,15 @@ def parse():
                     help="only copy a 256 MiB buffer 4 times (reference for HBM byte counters)")
     ap.add_argument("--workload", default="config2",
                     choices=["config2", "config2-mc", "config3", "config4", "config5", "paper-type1", "paper-type2",
-                             "paper-couplings"],
+                             "paper-couplings", "paper-theta"],
                     help="config2 (default): the bench line; the others print a report line: config2-mc "
                          "plain Monte Carlo on the finest config-2 level to the same eps, config3 "
                          "low-density MLMC with persistent rounds, config4 learned control variate, "
                          "config5 streaming-kernel throughput at 256^2..1024^2, paper-type1 the paper's own "
                          "Type-1 experiment (MLMC and MC at its accuracies, speed-ups against its table), "
                          "paper-type2 its variance-reduction factor against h_min, paper-couplings the "
-                         "symmetric NN and the Fourier coupling against the NN coupling")
+                         "symmetric NN and the Fourier coupling against the NN coupling, paper-theta "
+                         "explicit against Crank-Nicolson and implicit Euler time stepping")
     ap.add_argument("--N", type=float, default=None, help="particle number (config3: 1e5, config5: 1e6)")
     ap.add_argument("--samples", type=int, default=32, help="config5: finest-level pairs to time")
     ap.add_argument("--cv-levels", default=None, help="config4: comma-separated levels that use the control "
@@ -147,7 +148,7 @@ def main():
     if args.workload != "config2":
         {"config2-mc": bench_config2_mc, "config3": bench_config3, "config4": bench_config4,
          "config5": bench_config5, "paper-type1": bench_paper_type1,
-         "paper-type2": bench_paper_type2, "paper-couplings": bench_paper_couplings}[args.workload](args)
+         "paper-type2": bench_paper_type2, "paper-couplings": bench_paper_couplings, "paper-theta": bench_paper_theta}[args.workload](args)
         return
     base = W.config2(N=1e4)
 
@@ -393,6 +394,68 @@ def bench_paper_couplings(args):
     _report("couplings in the paper's Sec. 7 setting (NN vertex, NN cell-centred, Fourier; regular datum, N=2e9 "
             "and 2e5): level variances and Algorithm 1 at eps=10^-1.4..10^-2.6", last["work_ratio_nn_over_fourier"][-1],
             "NN/Fourier MLMC work ratio at eps=10^-2.6, N=2e9", out)
+
+
+def bench_paper_theta(args):
+    """Time stepping with the implicit weight b0 of eq. (FullyDiscreteDK) in the paper's Sec. 7
+    setting (regular datum, N = 2e9, grids 4^2 .. 64^2): the explicit scheme of the paper
+    (b0 = 0), Crank--Nicolson (b0 = 1/2) and implicit Euler (b0 = 1) at the paper's tau/h^2, and
+    implicit Euler with four times the time step (tau/h^2 = 4 x 0.415, beyond the explicit limit
+    1/2; hierarchy 8^2 .. 64^2).  Per scheme: level profile (args.samples * 125 samples per level: V_l, E[Y_l], kernel
+    rate) and Algorithm 1 at the paper's accuracies 10^-1.4 .. 10^-2.4 (work, wall time,
+    estimate)."""
+    import math
+    import torch
+    import dk_workloads as W
+    import paper_2311_08872_amd as dk
+    eps_list = [10 ** -1.4, 10 ** -1.7, 10 ** -2.0, 10 ** -2.2, 10 ** -2.4]
+    per_level = args.samples * 125
+    base = W.paper_reg(2e9).with_(levels=5)
+    # four times the step: tau_0 = 4 mu h_0^2 equals T on the 8 x 8 grid, so that hierarchy is
+    # 8^2 .. 64^2 with 1, 4, 16, 64 steps (a quarter of the explicit scheme's on each grid)
+    schemes = [("explicit", base), ("crank_nicolson", base.with_(b0=0.5)), ("implicit_euler", base.with_(b0=1.0)),
+               ("implicit_euler_4tau", base.with_(b0=1.0, mu=4 * base.mu, n0=8, levels=4))]
+    out = {}
+    ctx = dk.Context(0)
+    dk.estimate(base.with_(b0=0.5, seed=1000), 10 ** -1.4, ctx=ctx)          # warm-up (untimed)
+    ctx.close()
+    for name, p in schemes:
+        ctx = dk.Context(0)
+        prof = []
+        try:
+            for l in range(p.levels):
+                ctx.reset()
+                mom = dk.level_pair(p, l, 0, per_level, ctx=ctx)[0]
+                torch.cuda.synchronize()
+                st = [s_ for s_ in ctx.stats() if s_["level"] == l][0]
+                prof.append({"level": l, "n": p.n(l), "steps": p.steps(l), "V": mom.var, "Y": mom.mean,
+                             "cell_updates_per_s": st["cell_updates"] / (st["kernel_ms"] / 1e3)})
+        except dk.DKError as e:
+            print(f"[bench] paper theta {name}: {e}", file=sys.stderr, flush=True)
+            ctx.close()
+            continue
+        for l in range(2, p.levels):
+            prof[l]["beta"] = math.log(prof[l - 1]["V"] / prof[l]["V"]) / math.log(2.0)
+        vs = ", ".join("%.3g" % r_["V"] for r_ in prof)
+        ys = ", ".join("%.3g" % r_["Y"] for r_ in prof)
+        print(f"[bench] paper theta {name}: V_l = [{vs}], E[Y_l] = [{ys}]", file=sys.stderr, flush=True)
+        runs = []
+        for eps in eps_list:
+            ctx.reset(drop_tables=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = dk.estimate(p, eps, ctx=ctx)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            runs.append({"eps": eps, "L": r["L"], "converged": r["converged"], "M": r["M"], "estimate": r["estimate"][0],
+                         "cell_updates": r["cell_updates"], "wall_s": wall})
+            print(f"[bench] paper theta {name} eps={eps:.3g}: L={r['L']} converged={r['converged']} work "
+                  f"{r['cell_updates']:.3g}, {wall:.3f} s, estimate {r['estimate'][0]:.5f}", file=sys.stderr, flush=True)
+        ctx.close()
+        out[name] = {"b0": p.b0, "mu": p.mu, "steps": [p.steps(l) for l in range(p.levels)], "profile": prof, "alg1": runs}
+    _report("time stepping with implicit weight b0 in the paper's Sec. 7 setting (regular datum, N=2e9, 4^2..64^2): "
+            "explicit, Crank-Nicolson, implicit Euler, implicit Euler with 4x tau", out["crank_nicolson"]["alg1"][-1]["estimate"],
+            "Crank-Nicolson MLMC estimate at eps=10^-2.4", out)
 
 
 def bench_paper_type2(args):
