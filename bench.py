@@ -79,6 +79,8 @@ def parse():
                          "explicit against Crank-Nicolson and implicit Euler time stepping")
     ap.add_argument("--N", type=float, default=None, help="particle number (config3: 1e5, config5: 1e6)")
     ap.add_argument("--samples", type=int, default=32, help="config5: finest-level pairs to time")
+    ap.add_argument("--depth-only", action="store_true",
+                    help="config5: only the temporal-depth study (4 x --samples pairs, 128 x --samples steps)")
     ap.add_argument("--cv-levels", default=None, help="config4: comma-separated levels that use the control "
                                                         "variate (default: those where it lowers variance x cost)")
     return ap.parse_args()
@@ -625,8 +627,9 @@ def bench_config5(args):
     p = W.config5(N=N)
     out = {}
     ctx = dk.Context(0)
-    dk.level_pair(p, 4, 0, 64, ctx=ctx)                                 # warm-up (untimed)
-    for l in (4, 5, 6):
+    if not args.depth_only:
+        dk.level_pair(p, 4, 0, 64, ctx=ctx)                             # warm-up (untimed)
+    for l in (() if args.depth_only else (4, 5, 6)):
         cnt = args.samples * 4 ** (6 - l)
         ctx.reset()
         torch.cuda.synchronize()
@@ -647,19 +650,22 @@ def bench_config5(args):
     # at D != 4, the restricted-noise sums that go through HBM: per 4 fine steps D = 1: 64 + 14 + 6,
     # D = 2: 32 + 6 + 6, D = 4: 16 + 4; per 8 fine steps D = 8: 16 + 4 + 12.
     pair_bytes = {1: 84 / 4, 2: 44 / 4, 4: 20 / 4, 8: 32 / 8}
-    ps = p.with_(T=p.tau(6) * 4096, steps_policy=W.STEPS_EXACT)
-    assert ps.steps(6) == 4096
+    dsteps = min(4096, 128 * args.samples)              # 4096 at the default --samples 32
+    dcount = 4 * args.samples                           # 128 pairs at the default
+    ps = p.with_(n0=512, levels=2)                      # the 1024^2 / 512^2 pair as level 1
+    ps = ps.with_(T=ps.tau(1) * dsteps, steps_policy=W.STEPS_EXACT)
+    assert ps.n(1) == 1024 and ps.steps(1) == dsteps
     depths = {}
     for coupled in (True, False):
         for d in (1, 2, 4, 8):
             ctx.set_stream_depth(d)
             ctx.reset()
             if coupled:
-                dk.level_pair(ps, 6, 0, 128, ctx=ctx)
+                dk.level_pair(ps, 1, 0, dcount, ctx=ctx)
             else:
-                dk.mc_level(ps, 6, 0, 128, ctx=ctx)
+                dk.mc_level(ps, 1, 0, dcount, ctx=ctx)
             torch.cuda.synchronize()
-            st = [s for s in ctx.stats() if s["level"] == 6][0]
+            st = [s for s in ctx.stats() if s["level"] == 1][0]
             assert st["rows"] == -d
             fine = st["cell_updates"] / (1 + 1 / 16 if coupled else 1.0)
             rate = st["cell_updates"] / (st["kernel_ms"] / 1e3)
@@ -671,7 +677,7 @@ def bench_config5(args):
                   f"{by / 1e9:.0f} GB/s algorithmic ({100 * by / 8e12:.1f} % of 8 TB/s)", file=sys.stderr, flush=True)
     ctx.set_stream_depth(0)
     heat = {}
-    for n, batch in ((256, 4096), (1024, 256)):
+    for n, batch in (() if args.depth_only else ((256, 4096), (1024, 256))):
         x = torch.ones((batch, n, n), dtype=torch.float32, device="cuda")
         dk.heat_steps(x, 4, p.mu, ctx=ctx)
         dt = dk.heat_steps(x, 64, p.mu, ctx=ctx) / 1e3      # kernel time of the 64 steps
@@ -679,6 +685,10 @@ def bench_config5(args):
                         "frac_of_8TBps": 8.0 * batch * n * n * 64 / dt / 8e12}
         del x
     ctx.close()
+    if args.depth_only:
+        _report(f"config-5 streaming depths at 1024^2 ({dcount} pairs / paths, {dsteps} fine steps)",
+                depths["pair_D4"]["cell_updates_per_s"], "cell updates/s (pairs, depth 4)", {"depths_1024": depths})
+        return
     fin = out[f"{p.n(6)}"]
     _report(f"config-5 throughput: coupled pairs at 256^2, 512^2, 1024^2 (N={N:g}, tau=0.1h^2, "
             f"{args.samples} pairs at 1024^2), streaming kernel", fin["cell_updates_per_s"], "cell updates/s",
