@@ -13,12 +13,14 @@
 //
 // Layout: one block per sample (blocks stride over the batch), n <= 64.  LDS holds the state,
 // one direction of the step's normals (binary32, exact) and a complex work array.  The 2-D
-// transform is a radix-2 FFT over rows then columns in that array: decimation in time from
-// bit-reversed input for the forward transform, decimation in frequency with conjugate
-// twiddles for the inverse, so the increment is written to and read from bit-reversed
-// positions and no reordering pass is needed.  The coarse step reuses the work array (its
-// transform and its restricted noise sums use disjoint parts of it).  A thread owns 2 x 2 cell
-// blocks (two generator calls per step).
+// transform runs one row (or column) per group of n lanes with the butterflies across lanes by
+// shuffles: rows forward, then per column the forward transform, the multiplier and the inverse
+// without leaving registers, then rows inverse -- four barriers per filter.  Decimation in time
+// from bit-reversed input for the forward transforms and in frequency to bit-reversed output
+// for the inverse ones, so each pass reads or writes its own row or column in permuted order
+// and no separate reordering is needed.  The coarse step reuses the work array (its transform
+// and its restricted noise sums use disjoint parts of it).  A thread owns 2 x 2 cell blocks (two
+// generator calls per step).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -36,13 +38,10 @@ struct TG {
     static constexpr int NB = NC * NC;                                // 2 x 2 blocks
     static constexpr int THREADS = N >= 64 ? 512 : (N >= 32 ? 256 : 64);
     static constexpr int SLOTS = (NB + THREADS - 1) / THREADS;
-    static constexpr int LOG = N == 4 ? 2 : N == 8 ? 3 : N == 16 ? 4 : N == 32 ? 5 : 6;
 };
 
 template <typename Real>
 __device__ __forceinline__ Real tpsq(Real x) { return sqrt(x > Real(0) ? x : Real(0)); }
-
-__device__ __forceinline__ int rev_bits(int v, int bits) { return (int)(__builtin_bitreverse32((uint32_t)v) >> (32 - bits)); }
 
 template <typename V>
 __device__ __forceinline__ int t_after(int t, V v)
@@ -57,40 +56,94 @@ __device__ __forceinline__ double t_wave_sum(double v)
     return v;
 }
 
-// In-place 2-D transform of an M x M complex array (rows, then columns).  Forward: DIT from
-// bit-reversed input to natural order; inverse (unnormalised, conjugate twiddles): DIF from
-// natural order to bit-reversed output.  tw[k] = exp(-2 pi i k / NT), k < NT/2, M <= NT.
-template <typename Real, int M, int NT, int THREADS, bool INVERSE>
-__device__ void fft2d(Real* re, Real* im, const Real* tw, int t)
+// Radix-2 transform of M points held one per lane, in groups of M lanes (M <= 64), butterflies
+// across lanes by shuffles.  Forward: decimation in time, input in bit-reversed order, output in
+// natural order.  Inverse (unnormalised, conjugate twiddles): decimation in frequency, input in
+// natural order, output in bit-reversed order.  l is the lane's index in its group;
+// tw[k] = exp(-2 pi i k / NT), k < NT/2, M <= NT.
+template <typename Real, int M, int NT, bool INVERSE>
+__device__ __forceinline__ void lane_fft(Real& xr, Real& xi, int l, const Real* tw)
 {
 #pragma clang fp contract(off)
-    for (int pass = 0; pass < 2; ++pass) {
-        const int es = pass == 0 ? 1 : M;      // stride along a transform
-        const int ls = pass == 0 ? M : 1;      // stride between transforms
-        for (int s = 0; s < __builtin_ctz(M); ++s) {
-            const int len = INVERSE ? (M >> s) : (2 << s);
-            const int half = len >> 1;
-            for (int b = t; b < M * M / 2; b += THREADS) {
-                const int line = b / (M / 2), j = b - line * (M / 2);
-                const int grp = j / half, pos = j - grp * half;
-                const int i0 = grp * len + pos, i1 = i0 + half;
-                const int e0 = line * ls + i0 * es, e1 = line * ls + i1 * es;
-                const int k = pos * (NT / len);
-                const Real wr = tw[2 * k], wi = INVERSE ? -tw[2 * k + 1] : tw[2 * k + 1];
-                const Real ur = re[e0], ui = im[e0], vr = re[e1], vi = im[e1];
-                if (!INVERSE) {
-                    const Real tr = wr * vr - wi * vi, ti = wr * vi + wi * vr;
-                    re[e0] = ur + tr; im[e0] = ui + ti;
-                    re[e1] = ur - tr; im[e1] = ui - ti;
-                } else {
-                    const Real dr = ur - vr, di = ui - vi;
-                    re[e0] = ur + vr; im[e0] = ui + vi;
-                    re[e1] = dr * wr - di * wi; im[e1] = dr * wi + di * wr;
-                }
+    if constexpr (!INVERSE) {
+#pragma unroll
+        for (int h = 1; h < M; h <<= 1) {
+            const Real pr = __shfl_xor(xr, h, 64), pi = __shfl_xor(xi, h, 64);
+            const int k = (l & (h - 1)) * (NT / (2 * h));
+            const Real wr = tw[2 * k], wi = tw[2 * k + 1];
+            if ((l & h) == 0) {            // x[i] + w x[i + h]
+                xr = xr + (wr * pr - wi * pi);
+                xi = xi + (wr * pi + wi * pr);
+            } else {                       // x[i] - w x[i + h]
+                const Real tr = wr * xr - wi * xi, ti = wr * xi + wi * xr;
+                xr = pr - tr;
+                xi = pi - ti;
             }
-            __syncthreads();
+        }
+    } else {
+#pragma unroll
+        for (int h = M / 2; h >= 1; h >>= 1) {
+            const Real pr = __shfl_xor(xr, h, 64), pi = __shfl_xor(xi, h, 64);
+            const int k = (l & (h - 1)) * (NT / (2 * h));
+            const Real wr = tw[2 * k], wi = -tw[2 * k + 1];
+            if ((l & h) == 0) {            // u + v
+                xr = xr + pr;
+                xi = xi + pi;
+            } else {                       // (u - v) conj(w)
+                const Real dr = pr - xr, di = pi - xi;
+                xr = dr * wr - di * wi;
+                xi = dr * wi + di * wr;
+            }
         }
     }
+}
+
+// re <- (1/M^2) F^-1 (sol .* F re) for a real M x M array in LDS (natural order, [y][x]); im is
+// scratch.  Rows, then columns (forward transform, the multiplier and the inverse in registers),
+// then rows again: four barriers.  Every lane takes part in every shuffle; lanes past the last
+// row or column compute on zeros and store nothing.
+template <typename Real, int M, int NT, int THREADS>
+__device__ void filter2d(Real* re, Real* im, const Real* sol, const Real* tw, int t)
+{
+#pragma clang fp contract(off)
+    constexpr int PER = 64 / M;                       // rows (columns) per wavefront
+    constexpr int LOG = __builtin_ctz(M);
+    const int lane = t & 63, l = lane & (M - 1), g = lane / M, w = t >> 6;
+    const int rl = (int)(__builtin_bitreverse32((uint32_t)l) >> (32 - LOG));
+    constexpr int WAVES = THREADS / 64;
+    __syncthreads();
+    // rows: input at bit-reversed x, output natural kx
+    for (int r0 = w * PER; r0 < M; r0 += WAVES * PER) {
+        const int row = r0 + g;
+        Real xr = row < M ? re[row * M + rl] : Real(0), xi = Real(0);
+        lane_fft<Real, M, NT, false>(xr, xi, l, tw);
+        if (row < M) { re[row * M + l] = xr; im[row * M + l] = xi; }
+    }
+    __syncthreads();
+    // columns: forward from bit-reversed ky, multiplier, inverse to bit-reversed y
+    for (int c0 = w * PER; c0 < M; c0 += WAVES * PER) {
+        const int col = c0 + g;
+        Real xr = Real(0), xi = Real(0);
+        if (col < M) { xr = re[rl * M + col]; xi = im[rl * M + col]; }
+        lane_fft<Real, M, NT, false>(xr, xi, l, tw);
+        if (col < M) {
+            const Real sv = sol[l * M + col];
+            xr = xr * sv;
+            xi = xi * sv;
+        }
+        lane_fft<Real, M, NT, true>(xr, xi, l, tw);
+        if (col < M) { re[rl * M + col] = xr; im[rl * M + col] = xi; }
+    }
+    __syncthreads();
+    // rows: inverse from natural kx to bit-reversed x; real part, scaled
+    for (int r0 = w * PER; r0 < M; r0 += WAVES * PER) {
+        const int row = r0 + g;
+        Real xr = Real(0), xi = Real(0);
+        if (row < M) { xr = re[row * M + l]; xi = im[row * M + l]; }
+        lane_fft<Real, M, NT, true>(xr, xi, l, tw);
+        if (row < M) re[row * M + rl] = xr * (Real(1) / Real(M * M));
+    }
+    __syncthreads();
 }
 }  // namespace
 
@@ -99,7 +152,6 @@ __global__ void __launch_bounds__(TG<N>::THREADS) theta_kernel(const ThetaArgs A
 {
 #pragma clang fp contract(off)
     constexpr int THREADS = TG<N>::THREADS, NC = TG<N>::NC, NB = TG<N>::NB, SLOTS = TG<N>::SLOTS;
-    constexpr int LOG = TG<N>::LOG;
     constexpr int NN = N * N, NCC = NC * NC;
     constexpr bool KAHAN = sizeof(Real) == 4;
     __shared__ Real rho[NN];
@@ -116,7 +168,6 @@ __global__ void __launch_bounds__(TG<N>::THREADS) theta_kernel(const ThetaArgs A
     const Real* tw = (const Real*)A.tw;
     const Real* solf = (const Real*)A.sol_f;
     const Real* solc = (const Real*)A.sol_c;
-    const Real inv_nn = Real(1) / Real(NN), inv_ncc = Real(1) / Real(NCC);
 
     for (uint64_t si = blockIdx.x; si < A.count; si += gridDim.x) {
         const NoiseKey key = make_key(A.seed, A.tag, A.level_id, A.first + si);
@@ -211,22 +262,12 @@ __global__ void __launch_bounds__(TG<N>::THREADS) theta_kernel(const ThetaArgs A
                     const Real dy = tpsq(rho[cd]) * (Real)zr[cd] - tpsq(rho[cu]) * (Real)zr[cu];
                     const Real lap = fma(Real(-4), rv, (rho[cl] + rho[cr]) + (rho[cu] + rho[cd]));
                     const Real d = fma(kf, dv[k][q] + dy, a * lap);
-                    const int e = rev_bits(y, LOG) * N + rev_bits(x, LOG);
-                    wre[e] = d;
-                    wim[e] = Real(0);
+                    wre[c] = d;
                     dlast = d;
                 }
                 tq = t_after(tq, dlast);
             }
-            __syncthreads();
-            fft2d<Real, N, N, THREADS, false>(wre, wim, tw, t);
-            for (int e = t; e < NN; e += THREADS) {
-                const Real sv = solf[e];
-                wre[e] = wre[e] * sv;
-                wim[e] = wim[e] * sv;
-            }
-            __syncthreads();
-            fft2d<Real, N, N, THREADS, true>(wre, wim, tw, t);
+            filter2d<Real, N, N, THREADS>(wre, wim, solf, tw, t);
             // rho += S d (own cells only: every read of rho this step is behind a barrier)
             tq = t;
 #pragma unroll
@@ -237,7 +278,7 @@ __global__ void __launch_bounds__(TG<N>::THREADS) theta_kernel(const ThetaArgs A
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int x = 2 * bx + (q & 1), y = 2 * by + (q >> 1), c = y * N + x;
-                    const Real u = wre[rev_bits(y, LOG) * N + rev_bits(x, LOG)] * inv_nn;
+                    const Real u = wre[c];
                     const Real rv = rho[c];
                     if constexpr (KAHAN) {
                         const Real yk = u - cmp[k][q];
@@ -262,7 +303,6 @@ __global__ void __launch_bounds__(TG<N>::THREADS) theta_kernel(const ThetaArgs A
                         Z[k][0] = Z[k][1] = Real(0);
                     }
                     __syncthreads();
-                    constexpr int LOGC = LOG - 1;
 #pragma unroll
                     for (int k = 0; k < SLOTS; ++k) {
                         const int c = t + k * THREADS;
@@ -275,25 +315,15 @@ __global__ void __launch_bounds__(TG<N>::THREADS) theta_kernel(const ThetaArgs A
                         const Real dy = tpsq(rhoc[cd]) * zc1[cd] - tpsq(rhoc[cu]) * zc1[cu];
                         const Real lap = fma(Real(-4), rv, (rhoc[cl] + rhoc[cr]) + (rhoc[cu] + rhoc[cd]));
                         const Real d = fma(kc, dx + dy, a * lap);
-                        const int e = (LOGC > 0 ? rev_bits(y, LOGC) : 0) * NC + (LOGC > 0 ? rev_bits(x, LOGC) : 0);
-                        wre[e] = d;
-                        wim[e] = Real(0);
+                        wre[c] = d;
                     }
-                    __syncthreads();
-                    fft2d<Real, NC, N, THREADS, false>(wre, wim, tw, t);
-                    for (int e = t; e < NCC; e += THREADS) {
-                        const Real sv = solc[e];
-                        wre[e] = wre[e] * sv;
-                        wim[e] = wim[e] * sv;
-                    }
-                    __syncthreads();
-                    fft2d<Real, NC, N, THREADS, true>(wre, wim, tw, t);
+                    filter2d<Real, NC, N, THREADS>(wre, wim, solc, tw, t);
 #pragma unroll
                     for (int k = 0; k < SLOTS; ++k) {
                         const int c = t + k * THREADS;
                         if (c >= NCC) continue;
                         const int x = c % NC, y = c / NC;
-                        const Real u = wre[(LOGC > 0 ? rev_bits(y, LOGC) : 0) * NC + (LOGC > 0 ? rev_bits(x, LOGC) : 0)] * inv_ncc;
+                        const Real u = wre[c];
                         const Real rv = rhoc[c];
                         if constexpr (KAHAN) {
                             const Real yk = u - cmpc[k];
