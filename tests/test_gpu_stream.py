@@ -139,6 +139,26 @@ def test_stream_1024_pair_matches_oracle():
     assert float(rel.max()) <= 1e-5, rel.max()
 
 
+def test_stream_4096_pair_largest_grid():
+    """The largest grid the library accepts (4096^2 fine, 2048^2 coarse), one pair over 8 fine
+    steps at depth 4 and at depth 1, against the oracle."""
+    p = W.config5().with_(n0=2048, levels=2)
+    p = p.with_(T=p.tau(1) * 8, steps_policy=W.STEPS_EXACT)
+    assert p.n(1) == 4096 and p.steps(1) == 8
+    banner("stream 4096^2 pair vs oracle")
+    ref = oracle.run_range(oracle.OracleProblem(p), 1, 7, 1)
+    for depth in (4, 1):
+        ctx = dk.Context(0)
+        ctx.set_stream_depth(depth)
+        _, ps = dk.level_pair(p, 1, 7, 1, per_sample=True, ctx=ctx)
+        torch.cuda.synchronize()
+        gpu = ps.cpu().numpy()
+        rel = np.abs(gpu - ref) / np.maximum(np.abs(ref), 1e-3)
+        banner(f"depth {depth}: max relative error {rel.max():.3g}")
+        assert float(rel.max()) <= 1e-5, rel.max()
+        ctx.close()
+
+
 def test_noise_free_batch_matches_fourier_multiplier():
     """dk_heat_steps: each field evolves by the multiplier g_k^M of the noise-free scheme."""
     import math

@@ -66,6 +66,18 @@ def test_config2_theta_fp32_parity(level, count):
     assert err <= 1e-5
 
 
+def test_cell_centred_crank_nicolson():
+    """b0 = 1/2 on cell-centred grid points (the symmetric NN coupling): the two options compose."""
+    p = W.config2(N=1e4).with_(b0=0.5, levels=4, grid=W.GRID_CELL)
+    banner("b0=0.5 on cell centres, level 2")
+    _, ps = dk.level_pair(p, 2, 0, 24, per_sample=True)
+    torch.cuda.synchronize()
+    ref = theta.run_range(p, 2, 0, 24)
+    err = scaled_err(ps.cpu().numpy(), ref)
+    banner(f"scaled FP32-vs-FP64 error {err:.3g} (tolerance 1e-5)")
+    assert err <= 1e-5
+
+
 def test_large_time_step_implicit_euler():
     """b0 = 1 with tau = 2 h^2 (four times the explicit limit mu <= 1/2), T = 2 tau_0."""
     p = W.config2(N=1e4).with_(b0=1.0, levels=4, mu=2.0, T=0.0625)
