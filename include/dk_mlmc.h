@@ -355,26 +355,31 @@ int dk_context_stats(dk_context* ctx, dk_kernel_stats* out, int32_t max);
 /* Clears the records; also drops cached level tables and tuning choices when drop_tables != 0. */
 int dk_context_reset(dk_context* ctx, int32_t drop_tables);
 
-/* Tile shapes of the resident kernel: a lane owns 2 columns and R rows of an n x n grid.
- * dk_shape_rows(n, v) gives R of variant v (0 if the variant does not exist).  By default the
+/* Tile shapes of the resident kernel: a lane owns 2 columns and R rows of an n x n grid, and a
+ * block holds S samples (about 256 lanes, or four times as many samples in 1024-lane blocks).
+ * dk_shape_rows(n, v) gives R of variant v and dk_shape_spw(n, v) its S (both 0 if the variant
+ * does not exist).  By default the
  * context times the variants on a short batch the first time a large job (>= 1e11 cell updates)
  * runs a grid size, and keeps the fastest; dk_context_set_shape forces variant v for grid size
  * n (v < 0 restores the automatic choice).  Per-sample fields do not depend on the shape; the
  * observables' FP64 lane reduction order does (last-bit differences). */
 int dk_context_set_shape(dk_context* ctx, int32_t n, int32_t variant);
 int dk_shape_rows(int32_t n, int32_t variant);
+int dk_shape_spw(int32_t n, int32_t variant);
 
 /* The autotuner's tile-shape and streaming-depth choices of the context (and those loaded) as
  * JSON text:
  *   {"format": "dk-tile-shapes-1", "arch": "gfx950",
- *    "shapes": [{"n": 128, "pair": 1, "flux": 0, "rows": 8}, {"n": 1024, "pair": 1, "flux": 0,
- *               "depth": 4}, ...]}
+ *    "shapes": [{"n": 128, "pair": 1, "flux": 0, "rows": 8, "spw": 1}, {"n": 1024, "pair": 1,
+ *               "flux": 0, "depth": 4}, ...]}
+ * ("spw" may be left out of a shape entry: it then names the ~256-lane shape with that R)
  * Writes at most cap bytes including the terminating NUL into buf (buf may be NULL when cap is
  * 0) and returns the text's full length without the NUL, or a negative error code. */
 int dk_context_tuning_json(dk_context* ctx, char* buf, uint64_t cap);
 /* Loads choices in that format; listed shapes replace the context's choices and are used
  * without timing.  DK_EINVAL if the text lacks the format tag, names another architecture,
- * lists a row count that no compiled shape of that grid has, or a depth other than 1, 2, 4, 8.
+ * lists a row count (and samples per block) that no compiled shape of that grid has, or a depth
+ * other than 1, 2, 4, 8.
  * With the environment variable DK_TUNE_CACHE set to a file path, every context loads that file
  * when it is created (if it exists and is valid) and rewrites it whenever the autotuner makes a
  * new choice. */

@@ -161,6 +161,10 @@ class Context:
     def shape_rows(n: int, variant: int) -> int:
         return L.load().dk_shape_rows(n, variant)
 
+    @staticmethod
+    def shape_spw(n: int, variant: int) -> int:
+        return L.load().dk_shape_spw(n, variant)
+
     def reset(self, drop_tables: bool = False):
         _check(self.lib.dk_context_reset(self.h, int(drop_tables)))
 

@@ -96,6 +96,7 @@ SIGNATURES = {
     "dk_context_reset": (C.c_int, [C.c_void_p, C.c_int32]),
     "dk_context_set_shape": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "dk_shape_rows": (C.c_int, [C.c_int32, C.c_int32]),
+    "dk_shape_spw": (C.c_int, [C.c_int32, C.c_int32]),
     "dk_context_set_launch_cap": (C.c_int, [C.c_void_p, C.c_double]),
     "dk_context_tuning_json": (C.c_int, [C.c_void_p, C.c_char_p, C.c_uint64]),
     "dk_context_load_tuning_json": (C.c_int, [C.c_void_p, C.c_char_p]),

@@ -502,7 +502,8 @@ uint64_t chunk_size(int n_obs, double cells_per_sample, double max_cells)
 // ------------------------------------------------------------------------------------------
 // Tile-shape choices as JSON text:
 //   {"format": "dk-tile-shapes-1", "arch": "gfx950",
-//    "shapes": [{"n": 128, "pair": 1, "flux": 0, "rows": 8}, ...]}
+//    "shapes": [{"n": 128, "pair": 1, "flux": 0, "rows": 8, "spw": 1}, ...]}
+// ("spw", samples per block, may be left out: then the shape with that R and ~256-lane blocks)
 // ------------------------------------------------------------------------------------------
 std::string device_arch(int device)
 {
@@ -521,7 +522,7 @@ std::string tuning_json(const dk_context* ctx)
     for (const auto& kv : ctx->tuned) {
         const int nf = (int)(kv.first >> 8), pair = (int)((kv.first >> 4) & 0xF), flux = (int)(kv.first & 0xF);
         o << (first ? "" : ", ") << "{\"n\": " << nf << ", \"pair\": " << pair << ", \"flux\": " << flux
-          << ", \"rows\": " << dk::shape_rows(nf, kv.second) << "}";
+          << ", \"rows\": " << dk::shape_rows(nf, kv.second) << ", \"spw\": " << dk::shape_spw(nf, kv.second) << "}";
         first = false;
     }
     for (const auto& kv : ctx->tuned_depth) {
@@ -539,7 +540,7 @@ int load_tuning_json(dk_context* ctx, const std::string& text)
     static const std::regex fmt("\"format\"\\s*:\\s*\"dk-tile-shapes-1\"");
     static const std::regex arch("\"arch\"\\s*:\\s*\"([^\"]*)\"");
     static const std::regex entry("\\{\\s*\"n\"\\s*:\\s*(\\d+)\\s*,\\s*\"pair\"\\s*:\\s*(\\d+)\\s*,\\s*\"flux\"\\s*:\\s*(\\d+)"
-                                  "\\s*,\\s*\"rows\"\\s*:\\s*(\\d+)\\s*\\}");
+                                  "\\s*,\\s*\"rows\"\\s*:\\s*(\\d+)(?:\\s*,\\s*\"spw\"\\s*:\\s*(\\d+))?\\s*\\}");
     if (!std::regex_search(text, fmt)) return fail(DK_EINVAL, "tuning JSON: missing \"format\": \"dk-tile-shapes-1\"");
     std::smatch m;
     if (!std::regex_search(text, m, arch)) return fail(DK_EINVAL, "tuning JSON: missing \"arch\"");
@@ -564,6 +565,12 @@ int load_tuning_json(dk_context* ctx, const std::string& text)
         int v = 0;
         while (dk::shape_rows(nf, v) > 0 && dk::shape_rows(nf, v) != rows) ++v;
         if (dk::shape_rows(nf, v) == 0) return fail(DK_EINVAL, "tuning JSON: no %d-row shape for n = %d", rows, nf);
+        if ((*it)[5].matched) {
+            const int spw = std::stoi((*it)[5]);
+            while (dk::shape_rows(nf, v) > 0 && !(dk::shape_rows(nf, v) == rows && dk::shape_spw(nf, v) == spw)) ++v;
+            if (dk::shape_rows(nf, v) == 0)
+                return fail(DK_EINVAL, "tuning JSON: no %d-row shape with %d samples per block for n = %d", rows, spw, nf);
+        }
         got[((long)nf << 8) | ((long)pair << 4) | (long)flux] = v;
     }
     for (const auto& kv : got) ctx->tuned[kv.first] = kv.second;
@@ -640,8 +647,9 @@ int choose_shape(dk_context* ctx, const dk_problem* p, bool pair, const dk::Leve
     save_tuning_cache(ctx);
     if (std::getenv("DK_LOG")) {
         std::fprintf(stderr, "[dk] tuned n=%d pair=%d flux=%d:", nf, (int)pair, p->flux);
-        for (auto& kv : ctx->tune_log) std::fprintf(stderr, " R=%d %.3f ms", dk::shape_rows(nf, kv.first), kv.second);
-        std::fprintf(stderr, " -> R=%d\n", dk::shape_rows(nf, bestv));
+        for (auto& kv : ctx->tune_log)
+            std::fprintf(stderr, " R=%d/S=%d %.3f ms", dk::shape_rows(nf, kv.first), dk::shape_spw(nf, kv.first), kv.second);
+        std::fprintf(stderr, " -> R=%d/S=%d\n", dk::shape_rows(nf, bestv), dk::shape_spw(nf, bestv));
         std::fflush(stderr);
     }
     *variant = bestv;
@@ -2263,6 +2271,8 @@ int dk_context_set_shape(dk_context* ctx, int32_t n, int32_t variant)
 }
 
 int dk_shape_rows(int32_t n, int32_t variant) { return dk::shape_rows(n, variant); }
+
+int dk_shape_spw(int32_t n, int32_t variant) { return dk::shape_spw(n, variant); }
 
 int dk_heat_steps(dk_context* ctx, int32_t n, int32_t batch, int32_t steps, double mu, float* rho, float* work,
                   double* kernel_ms, void* stream)

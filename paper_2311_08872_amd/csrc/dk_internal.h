@@ -46,6 +46,8 @@ hipError_t launch_level(const LevelKind& k, const LevelArgs& a, hipStream_t s);
 bool level_supported(int nf);
 // rows per lane of tile-shape variant v for grid size nf, 0 if the variant does not exist
 int shape_rows(int nf, int v);
+// samples per block of tile-shape variant v for grid size nf, 0 if the variant does not exist
+int shape_spw(int nf, int v);
 
 // Ordered, compensated per-observable moment sums of a per-sample buffer.
 // out: device [n_obs][DK_NMOM][2] (sum, compensation).

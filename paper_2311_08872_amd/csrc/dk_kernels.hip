@@ -29,9 +29,10 @@ level_kernel(const LevelArgs A)
 
 // ---------------------------------------------------------------------------------------
 // Tile shapes.  A lane owns C = 2 columns and R rows; a sample uses (NF/2) x (NF/R) lanes and a
-// block holds SPW samples (about 256 lanes).  Several R per grid size are compiled for the FP32
-// noisy kernels; the host picks one by timing them (autotuning).  The other variants (FP64 state,
-// noise-free mean field) use the first shape.
+// block holds SPW samples (about 256 lanes, or four times as many samples in 1024-lane blocks).
+// Several (R, SPW) per grid size are compiled for the FP32 noisy kernels; the host picks one by
+// timing them (autotuning).  The other variants (FP64 state, noise-free mean field) use the
+// first shape.
 // ---------------------------------------------------------------------------------------
 // rows per lane of shape variant v for grid size nf (0 = no such variant); variant 0 is the
 // default (8 rows: the fastest measured on MI355X for every grid size of the hierarchy)
@@ -39,19 +40,31 @@ int shape_rows(int nf, int v)
 {
     switch (nf) {
         case 4: return v == 0 ? 4 : 0;
-        case 8: { const int r[] = {8, 2, 4}; return v < 3 ? r[v] : 0; }
-        case 16: { const int r[] = {8, 4, 2}; return v < 3 ? r[v] : 0; }
-        case 32: { const int r[] = {8, 4, 16}; return v < 3 ? r[v] : 0; }
-        case 64: { const int r[] = {8, 16}; return v < 2 ? r[v] : 0; }
+        case 8: { const int r[] = {8, 2, 4, 8}; return v < 4 ? r[v] : 0; }
+        case 16: { const int r[] = {8, 4, 2, 8}; return v < 4 ? r[v] : 0; }
+        case 32: { const int r[] = {8, 4, 16, 8}; return v < 4 ? r[v] : 0; }
+        case 64: { const int r[] = {8, 16, 8}; return v < 3 ? r[v] : 0; }
         case 128: { const int r[] = {8, 16}; return v < 2 ? r[v] : 0; }
         default: return 0;
     }
 }
 
-template <typename Real, int NF, int R, bool PAIR, int FLUX, bool NOISE>
+// samples per block of shape variant v (0 = no such variant): the last variant of 8^2 .. 64^2
+// is the default shape with four times the samples per block
+int shape_spw(int nf, int v)
+{
+    const int r = shape_rows(nf, v);
+    if (r == 0) return 0;
+    const int ts = (nf / 2) * (nf / r);
+    const int base = ts >= 256 ? 1 : 256 / ts;
+    const bool wide = (nf == 8 || nf == 16 || nf == 32) ? v == 3 : (nf == 64 ? v == 2 : false);
+    return wide ? 4 * base : base;
+}
+
+template <typename Real, int NF, int R, bool PAIR, int FLUX, bool NOISE, int X = 1>
 static hipError_t launch_R(const LevelArgs& A, hipStream_t s)
 {
-    using S = ShapeOf<NF, R>;
+    using S = ShapeOf<NF, R, X>;
     const uint64_t blocks = (A.count + S::SPW - 1) / S::SPW;
     if (blocks == 0) return hipSuccess;
     if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
@@ -72,23 +85,27 @@ static hipError_t launch_variants(const LevelArgs& A, int v, hipStream_t s)
         if constexpr (TUNED) {
             if (v == 1) return launch_R<Real, 8, 2, PAIR, FLUX, NOISE>(A, s);
             if (v == 2) return launch_R<Real, 8, 4, PAIR, FLUX, NOISE>(A, s);
+            if (v == 3) return launch_R<Real, 8, 8, PAIR, FLUX, NOISE, 4>(A, s);
         }
         return launch_R<Real, 8, 8, PAIR, FLUX, NOISE>(A, s);
     } else if constexpr (NF == 16) {
         if constexpr (TUNED) {
             if (v == 1) return launch_R<Real, 16, 4, PAIR, FLUX, NOISE>(A, s);
             if (v == 2) return launch_R<Real, 16, 2, PAIR, FLUX, NOISE>(A, s);
+            if (v == 3) return launch_R<Real, 16, 8, PAIR, FLUX, NOISE, 4>(A, s);
         }
         return launch_R<Real, 16, 8, PAIR, FLUX, NOISE>(A, s);
     } else if constexpr (NF == 32) {
         if constexpr (TUNED) {
             if (v == 1) return launch_R<Real, 32, 4, PAIR, FLUX, NOISE>(A, s);
             if (v == 2) return launch_R<Real, 32, 16, PAIR, FLUX, NOISE>(A, s);
+            if (v == 3) return launch_R<Real, 32, 8, PAIR, FLUX, NOISE, 4>(A, s);
         }
         return launch_R<Real, 32, 8, PAIR, FLUX, NOISE>(A, s);
     } else if constexpr (NF == 64) {
         if constexpr (TUNED) {
             if (v == 1) return launch_R<Real, 64, 16, PAIR, FLUX, NOISE>(A, s);
+            if (v == 2) return launch_R<Real, 64, 8, PAIR, FLUX, NOISE, 4>(A, s);
         }
         return launch_R<Real, 64, 8, PAIR, FLUX, NOISE>(A, s);
     } else {

@@ -498,13 +498,13 @@ __device__ __forceinline__ void level_body(const LevelArgs& A, uint64_t local0, 
     }
 }
 
-// Lanes per sample (TS) and samples per block (SPW, about 256 lanes) of a tile shape with C = 2
-// columns and R rows per lane.
-template <int NF, int R>
+// Lanes per sample (TS) and samples per block (SPW) of a tile shape with C = 2 columns and R rows
+// per lane: about 256 lanes per block, or X times as many samples (X = 4: 1024-lane blocks).
+template <int NF, int R, int X = 1>
 struct ShapeOf {
     static constexpr int C = 2;
     static constexpr int TS = (NF / C) * (NF / R);
-    static constexpr int SPW = TS >= 256 ? 1 : 256 / TS;
+    static constexpr int SPW = (TS >= 256 ? 1 : 256 / TS) * X;
 };
 
 // Neumaier's compensated summation step: s + c accumulates x.

@@ -30,7 +30,8 @@ def test_shape_variants_agree(level, flux):
     ref = None
     v = 0
     while dk.Context.shape_rows(n, v) > 0:
-        print(f"[gpu] shapes level={level} flux={flux} variant={v} rows={dk.Context.shape_rows(n, v)}", flush=True)
+        print(f"[gpu] shapes level={level} flux={flux} variant={v} rows={dk.Context.shape_rows(n, v)} "
+              f"spw={dk.Context.shape_spw(n, v)}", flush=True)
         ctx.set_shape(n, v)
         out = dk.level_fields(p, level, coupled, 11, count, ctx=ctx)
         torch.cuda.synchronize()
