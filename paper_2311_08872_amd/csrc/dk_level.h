@@ -162,6 +162,19 @@ __device__ __forceinline__ void sample_sync()
     else __syncthreads();
 }
 
+// Issue priority of a wavefront by its progress through one step: 3 from the start of the step
+// (the halo barrier) through row 1, then 2, 1, 0 over the remaining rows.  The SIMD's arbiter
+// otherwise favours the oldest wavefront, which runs ahead and waits at the next barrier while the
+// last ones finish with few wavefronts left to hide their latencies; ranking by progress keeps the
+// wavefronts of a sample level.
+template <bool ON, int LEVEL>
+__device__ __forceinline__ void progress_prio()
+{
+    if constexpr (ON) __builtin_amdgcn_s_setprio(LEVEL);
+}
+
+constexpr int row_prio(int i, int R) { return i < 2 ? 3 : 2 - (i - 2) * 3 / (R - 2); }
+
 template <typename Real, int R, int C, int FLUX, bool NOISE, bool COMP, bool ONE_BARRIER, bool WAVE_LOCAL, class Noise>
 __device__ __forceinline__ void tile_step(Real (&rho)[R][C], Real (&cmp)[R][C], Noise& noise, const Real a, const Real kappa,
                                           Real* __restrict__ halo, const int g, const int G, const int cl,
@@ -170,6 +183,8 @@ __device__ __forceinline__ void tile_step(Real (&rho)[R][C], Real (&cmp)[R][C], 
     // Every rounding step of the update is written out (fma where intended), so a cell's value
     // does not depend on how the compiler schedules a particular tile shape.
 #pragma clang fp contract(off)
+    constexpr bool BALANCE = !WAVE_LOCAL;
+    progress_prio<BALANCE, 3>();
     Real w0_first[C], w1_first[C], w0_last[C], w1_last[C];
     if constexpr (NOISE) {
         noise.template row<0>(w0_first, w1_first);
@@ -226,6 +241,7 @@ __device__ __forceinline__ void tile_step(Real (&rho)[R][C], Real (&cmp)[R][C], 
 
     RowLoop<0, R>::run([&](auto Ic) {
         constexpr int i = decltype(Ic)::value;
+        if constexpr (i >= 2 && row_prio(i, R) != row_prio(i - 1, R)) progress_prio<BALANCE, row_prio(i, R)>();
         Real rnext[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) rnext[c] = (i + 1 < R) ? rho[(i + 1 < R) ? i + 1 : 0][c] : rho_dn[c];
