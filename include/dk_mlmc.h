@@ -282,6 +282,14 @@ int dk_noise_dump(dk_context* ctx, uint64_t seed, uint32_t tag, int32_t level, i
                   uint64_t first_sample, uint32_t n_samples, int32_t first_step,
                   int32_t n_steps, float* out, void* stream);
 
+/* The generator's Gaussian transform alone (Box-Muller, Sec. 7's standard normals; the fixed
+ * binary32 sequence documented with the generator): for i < count, (z0[i], z1[i]) are the two
+ * normals of the Philox output words (a[i], b[i]), a the radius word and b the angle word, as
+ * used for every site.  a, b, z0, z1: DEVICE arrays of count elements.  For parity checks of
+ * the transform over chosen words (e.g. every radius word); DK_EINVAL on NULL arrays. */
+int dk_gauss_transform(dk_context* ctx, const uint32_t* a, const uint32_t* b, uint64_t count,
+                       float* z0, float* z1, void* stream);
+
 /* Final density fields of a batch (for field-level checks): rho_f_out [n_samples][n_l^2] and,
  * for coupled pairs, rho_c_out [n_samples][n_{l-1}^2], DEVICE, element type float for
  * DK_PREC_F32 and double for DK_PREC_F64.  coupled = 0 runs uncoupled level-l paths. */

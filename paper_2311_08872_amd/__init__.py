@@ -304,6 +304,21 @@ def noise_dump(seed: int, tag: int, level: int, n: int, first_sample: int, n_sam
     return out
 
 
+def gauss_transform(a, b, ctx: Context | None = None):
+    """dk_gauss_transform: the generator's two normals of each word pair (a[i], b[i]).  a, b:
+    int32 device tensors holding the uint32 words (same length); returns float32 (z0, z1)."""
+    ctx = ctx or default_context()
+    torch = _torch()
+    if a.dtype != torch.int32 or b.dtype != torch.int32 or a.shape != b.shape or not a.is_cuda or not b.is_cuda:
+        raise DKError(-1, "a and b must be int32 CUDA tensors of one shape")
+    a = a.contiguous()
+    b = b.contiguous()
+    z0 = torch.empty(a.shape, dtype=torch.float32, device=a.device)
+    z1 = torch.empty(a.shape, dtype=torch.float32, device=a.device)
+    _check(ctx.lib.dk_gauss_transform(ctx.h, _ptr(a), _ptr(b), a.numel(), _ptr(z0), _ptr(z1), ctx.stream()))
+    return z0, z1
+
+
 def level_fields(problem, level: int, coupled: bool, first: int, n: int, tag: int = W.TAG_MLMC,
                  ctx: Context | None = None):
     """dk_level_fields: (per-sample (n, n_obs, 2), rho_f (n, nf, nf), rho_c (n, nc, nc) or None)."""

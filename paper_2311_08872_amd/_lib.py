@@ -78,6 +78,8 @@ SIGNATURES = {
                                    C.POINTER(dk_mlmc_result), C.POINTER(dk_moments), C.c_void_p]),
     "dk_meanfield": (C.c_int, [C.c_void_p, C.POINTER(dk_problem), C.c_int32, C.POINTER(C.c_double), C.c_void_p,
                                C.c_void_p]),
+    "dk_gauss_transform": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
+                                     C.c_void_p]),
     "dk_noise_dump": (C.c_int, [C.c_void_p, C.c_uint64, C.c_uint32, C.c_int32, C.c_int32, C.c_uint64, C.c_uint32,
                                 C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
     "dk_level_fields": (C.c_int, [C.c_void_p, C.POINTER(dk_problem), C.c_int32, C.c_int32, C.c_uint64, C.c_uint64,

@@ -2402,6 +2402,17 @@ int dk_noise_dump(dk_context* ctx, uint64_t seed, uint32_t tag, int32_t level, i
     return DK_OK;
 }
 
+int dk_gauss_transform(dk_context* ctx, const uint32_t* a, const uint32_t* b, uint64_t count, float* z0, float* z1,
+                       void* stream)
+{
+    if (!ctx) return fail(DK_EINVAL, "context is NULL");
+    if (count == 0) return DK_OK;
+    if (!a || !b || !z0 || !z1) return fail(DK_EINVAL, "NULL argument");
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(dk::launch_gauss(a, b, count, z0, z1, (hipStream_t)stream));
+    return DK_OK;
+}
+
 int dk_alg1_host(double eps, int32_t L_max, const double* cost, const dk_mlmc_opts* opts, dk_level_sampler sampler,
                  void* user, dk_mlmc_result* out)
 {

@@ -67,6 +67,7 @@ hipError_t launch_field_eval(const FieldDev& f, double box, int n, void* out, bo
 hipError_t launch_noise_dump(uint64_t seed, uint32_t tag, int level, int n, uint64_t first_sample,
                              uint32_t n_samples, int first_step, int n_steps, float* out,
                              hipStream_t s);
+hipError_t launch_gauss(const uint32_t* a, const uint32_t* b, uint64_t count, float* z0, float* z1, hipStream_t s);
 
 // Noise-free FP64 stepping for grids that do not fit on chip: one launch per step.
 hipError_t launch_meanfield_stream(int n, double a, int steps, double* buf0, double* buf1,

@@ -287,6 +287,26 @@ hipError_t launch_noise_dump(uint64_t seed, uint32_t tag, int level, int n, uint
     return hipGetLastError();
 }
 
+__global__ void gauss_kernel(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b, uint64_t count,
+                             float* __restrict__ z0, float* __restrict__ z1)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    float u, v;
+    box_muller(a[i], b[i], u, v);
+    z0[i] = u;
+    z1[i] = v;
+}
+
+hipError_t launch_gauss(const uint32_t* a, const uint32_t* b, uint64_t count, float* z0, float* z1, hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    const uint64_t blocks = (count + 255) / 256;
+    if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(gauss_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, b, count, z0, z1);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------------------
 // Streaming noise-free FP64 step for large grids (one launch per step) and inner products.
 // ---------------------------------------------------------------------------------------

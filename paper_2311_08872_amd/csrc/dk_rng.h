@@ -43,6 +43,25 @@ __device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1)
     return c;
 }
 
+// Correctly rounded square root of a positive normal binary32 x.  The hardware estimate s is
+// within one ulp of sqrt(x), so the rounded root is s or a neighbour s-, s+ of it.  sqrt(x) lies
+// below the midpoint of two adjacent floats c < c+ exactly when x <= c c+: x - c c+ is a whole
+// multiple of ulp(c)^2, while the squared midpoint exceeds c c+ by ulp(c)^2 / 4, so no float x
+// lies in between; and a single-rounding fma gives the sign of x - c c+ exactly.  Hence the
+// result is s- if fma(-s-, s, x) <= 0, s+ if fma(-s+, s, x) > 0, and s otherwise.  The radius
+// argument -2 ln u lies in [1.1e-7, 33.3], so the scaling of subnormal inputs and the zero and
+// infinity cases of a general square root are not needed.
+__device__ __forceinline__ float sqrt_rn_normal(float x)
+{
+    const float s = __builtin_amdgcn_sqrtf(x);
+    const float sm = __uint_as_float(__float_as_uint(s) - 1u);
+    const float sp = __uint_as_float(__float_as_uint(s) + 1u);
+    const float rm = __builtin_fmaf(-sm, s, x);
+    const float rp = __builtin_fmaf(-sp, s, x);
+    const float r = rm <= 0.0f ? sm : s;
+    return rp > 0.0f ? sp : r;
+}
+
 // The sequence below is that definition written with integer bit operations where the
 // definition selects or negates (the same values, bit for bit, without lane-mask hazards):
 //   the fold:  m > binary32(1.41421356) iff the significand field of (float)w exceeds 0x3504f3;
@@ -58,26 +77,31 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, fl
     const float m = __uint_as_float(mant | ((127u - fold) << 23));   // in [sqrt(1/2), sqrt(2)]
     const float ne = (float)((int)(wb >> 23) + (int)fold - 151);     // e - 24
     const float xm = m - 1.0f;   // exact
-    float gx = __builtin_fmaf(0x1.0d33dap-4f, xm, -0x1.dbfb56p-4f);
-    gx = __builtin_fmaf(gx, xm, 0x1.e94d9cp-4f);
-    gx = __builtin_fmaf(gx, xm, -0x1.fcc1c0p-4f);
-    gx = __builtin_fmaf(gx, xm, 0x1.231156p-3f);
-    gx = __builtin_fmaf(gx, xm, -0x1.5554c0p-3f);
-    gx = __builtin_fmaf(gx, xm, 0x1.99a6e4p-3f);
-    gx = __builtin_fmaf(gx, xm, -0x1.00002ap-2f);
-    gx = __builtin_fmaf(gx, xm, 0x1.555540p-2f);
-    gx = __builtin_fmaf(gx, xm, -0.5f);
+    // -2 ln u, evaluated as -2 (hi + lo) of the definition: every coefficient and constant below
+    // carries the factor -2, which is exact (a power of two, no underflow or overflow in this
+    // range), so each rounded step yields exactly -2 times the defined step and the sum is
+    // exactly -2 (hi + lo), without a multiplication of its own.
+    float gx = __builtin_fmaf(-0x1.0d33dap-3f, xm, 0x1.dbfb56p-3f);
+    gx = __builtin_fmaf(gx, xm, -0x1.e94d9cp-3f);
+    gx = __builtin_fmaf(gx, xm, 0x1.fcc1c0p-3f);
+    gx = __builtin_fmaf(gx, xm, -0x1.231156p-2f);
+    gx = __builtin_fmaf(gx, xm, 0x1.5554c0p-2f);
+    gx = __builtin_fmaf(gx, xm, -0x1.99a6e4p-2f);
+    gx = __builtin_fmaf(gx, xm, 0x1.00002ap-1f);
+    gx = __builtin_fmaf(gx, xm, -0x1.555540p-1f);
     gx = __builtin_fmaf(gx, xm, 1.0f);
-    const float lnm = xm * gx;
-    const float hi = ne * 0x1.62ep-1f;
-    const float lo = __builtin_fmaf(ne, (float)(0.69314718055994530942 - 0.693115234375), lnm);
-    const float R = __builtin_sqrtf(-2.0f * (hi + lo));   // correctly rounded (built with -fhip-fp32-correctly-rounded-divide-sqrt)
+    gx = __builtin_fmaf(gx, xm, -2.0f);
+    const float lnm = xm * gx;                                          // -2 x g(x)
+    const float hi = ne * -0x1.62ep+0f;                                 // -2 (e - 24) ln2_hi
+    const float lo = __builtin_fmaf(ne, -2.0f * (float)(0.69314718055994530942 - 0.693115234375), lnm);
+    const float R = sqrt_rn_normal(hi + lo);                            // correctly rounded
 
     const uint32_t q = b >> 30;
     const uint32_t flip = (b >> 29) & 1u;                    // f > 1/2
     const uint32_t j = ((b >> 7) & 0x7FFFFFu) ^ ((0u - flip) & 0x7FFFFFu);
-    const float g = (float)((j << 1) | 1u) * 0x1p-24f;       // f, or 1 - f when f > 1/2
-    const float x = g * 0x1.921fb6p+0f;
+    // x = binary32(pi/2) g with g = f or 1 - f (when f > 1/2) = (2 j + 1) 2^-24; the scaling by
+    // 2^-24 is exact, so one product with binary32(pi/2) 2^-24 rounds to the same x
+    const float x = (float)((j << 1) | 1u) * (0x1.921fb6p+0f * 0x1p-24f);
     const float x2 = x * x;
     float ps = __builtin_fmaf(1.0f / 362880.0f, x2, -1.0f / 5040.0f);
     ps = __builtin_fmaf(ps, x2, 1.0f / 120.0f);
