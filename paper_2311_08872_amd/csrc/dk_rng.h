@@ -96,7 +96,7 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, fl
     const float lo = __builtin_fmaf(ne, -2.0f * (float)(0.69314718055994530942 - 0.693115234375), lnm);
     const float R = sqrt_rn_normal(hi + lo);                            // correctly rounded
 
-    const uint32_t q = b >> 30;
+    // quadrant q = b >> 30
     const uint32_t flip = (b >> 29) & 1u;                    // f > 1/2
     const uint32_t j = ((b >> 7) & 0x7FFFFFu) ^ ((0u - flip) & 0x7FFFFFu);
     // x = binary32(pi/2) g with g = f or 1 - f (when f > 1/2) = (2 j + 1) 2^-24; the scaling by
@@ -113,14 +113,15 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, fl
     pc = __builtin_fmaf(pc, x2, -0.5f);
     const float cs = __builtin_fmaf(x2, pc, 1.0f);
     // cos and sin of the quadrant's angle; each odd quarter turn swaps them, and the signs of
-    // cos and sin flip in quadrants (1, 2) and (2, 3)
-    const bool swap = (flip ^ (q & 1u)) != 0u;
+    // cos and sin flip in quadrants (1, 2) and (2, 3).  With t = b ^ (b << 1): bit 30 of t is
+    // flip ^ (q & 1), the swap, and bit 31 of t is the parity of q's two bits, the cosine's sign;
+    // the sine's sign is q's high bit, bit 31 of b.
+    const uint32_t t = b ^ (b << 1);
+    const bool swap = (t & 0x40000000u) != 0u;
     const float c = swap ? sn : cs;
     const float s = swap ? cs : sn;
-    const uint32_t csign = ((q ^ (q >> 1)) & 1u) << 31;
-    const uint32_t ssign = (q >> 1) << 31;
-    z0 = R * __uint_as_float(__float_as_uint(c) ^ csign);
-    z1 = R * __uint_as_float(__float_as_uint(s) ^ ssign);
+    z0 = R * __uint_as_float(__float_as_uint(c) ^ (t & 0x80000000u));
+    z1 = R * __uint_as_float(__float_as_uint(s) ^ (b & 0x80000000u));
 }
 
 // Normals of the horizontal site pair (2a, y), (2a+1, y) at fine step m.
