@@ -52,8 +52,12 @@ __device__ __forceinline__ double lane_get(int addr, double v)
 
 template <typename Real>
 __device__ __forceinline__ Real pos_sqrt(Real x) { return x > Real(0) ? sqrt(x) : Real(0); }
+// [x]^+ as a signed integer maximum of the bits: a negative binary32 (and -0) has a negative bit
+// pattern and becomes +0, a positive one is kept; one instruction, where fmaxf in IEEE mode
+// adds a NaN-quieting step (the state is finite, so the two agree)
+__device__ __forceinline__ float pos_part_f32(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
 template <>
-__device__ __forceinline__ float pos_sqrt<float>(float x) { return __builtin_amdgcn_sqrtf(__builtin_fmaxf(x, 0.0f)); }
+__device__ __forceinline__ float pos_sqrt<float>(float x) { return __builtin_amdgcn_sqrtf(pos_part_f32(x)); }
 
 // ---------------------------------------------------------------------------------------
 // Noise sources for one tile step: row(i, w0, w1) yields the unit noise of the tile's row i

@@ -99,9 +99,11 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, fl
     // quadrant q = b >> 30
     const uint32_t flip = (b >> 29) & 1u;                    // f > 1/2
     const uint32_t j = ((b >> 7) & 0x7FFFFFu) ^ ((0u - flip) & 0x7FFFFFu);
-    // x = binary32(pi/2) g with g = f or 1 - f (when f > 1/2) = (2 j + 1) 2^-24; the scaling by
-    // 2^-24 is exact, so one product with binary32(pi/2) 2^-24 rounds to the same x
-    const float x = (float)((j << 1) | 1u) * (0x1.921fb6p+0f * 0x1p-24f);
+    // x = binary32(pi/2) g with g = f or 1 - f (when f > 1/2) = (2 j + 1) 2^-24.  The scaling by
+    // 2^-24 is exact, and fma(j, 2 C, C) with C = binary32(pi/2) 2^-24 rounds the same real
+    // number (2 j + 1) C once, so x is the defined product.
+    constexpr float C = 0x1.921fb6p+0f * 0x1p-24f;
+    const float x = __builtin_fmaf((float)j, 2.0f * C, C);
     const float x2 = x * x;
     float ps = __builtin_fmaf(1.0f / 362880.0f, x2, -1.0f / 5040.0f);
     ps = __builtin_fmaf(ps, x2, 1.0f / 120.0f);

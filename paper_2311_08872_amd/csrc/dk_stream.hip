@@ -49,7 +49,9 @@ struct Geo {
 };
 
 __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
-__device__ __forceinline__ float psq(float x) { return __builtin_amdgcn_sqrtf(__builtin_fmaxf(x, 0.0f)); }
+// sqrt([x]^+) with [x]^+ as a signed integer maximum of the bits (negative values and -0 become
+// +0), the same as the resident kernel's, one instruction shorter than fmaxf in IEEE mode
+__device__ __forceinline__ float psq(float x) { return __builtin_amdgcn_sqrtf(__int_as_float(max(__float_as_int(x), 0))); }
 }  // namespace
 
 template <int FLUX, bool PAIR, int D>
