@@ -71,12 +71,14 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, fl
 {
 #pragma clang fp contract(off)
     const uint32_t w = ((a >> 9) << 1) | 1u;                 // odd, < 2^24, so (float)w is exact
-    const uint32_t wb = __float_as_uint((float)w);
-    const uint32_t mant = wb & 0x7FFFFFu;
-    const uint32_t fold = (0x3504F3u - mant) >> 31;          // 1 iff w 2^-e > binary32(1.41421356)
-    const float m = __uint_as_float(mant | ((127u - fold) << 23));   // in [sqrt(1/2), sqrt(2)]
-    const float ne = (float)((int)(wb >> 23) + (int)fold - 151);     // e - 24
-    const float xm = m - 1.0f;   // exact
+    // w = 2^e m1 with m1 in [1, 2) is m0 2^(e + 1) with m0 = m1 / 2 (frexp); the fold (m1 above
+    // binary32(1.41421356), i.e. m0 above half of it) takes m = m0, else m = m1 = 2 m0, and
+    // x = m - 1 is exact either way
+    const float wf = (float)w;
+    const float m0 = __builtin_amdgcn_frexp_mantf(wf);
+    const int fold = m0 > 0x1.6a09e6p-1f ? 1 : 0;
+    const float ne = (float)(__builtin_amdgcn_frexp_expf(wf) - 25 + fold);   // e - 24 of the folded m
+    const float xm = __builtin_fmaf(m0, fold ? 1.0f : 2.0f, -1.0f);        // m - 1, exact
     // -2 ln u, evaluated as -2 (hi + lo) of the definition: every coefficient and constant below
     // carries the factor -2, which is exact (a power of two, no underflow or overflow in this
     // range), so each rounded step yields exactly -2 times the defined step and the sum is
@@ -119,11 +121,12 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, fl
     // flip ^ (q & 1), the swap, and bit 31 of t is the parity of q's two bits, the cosine's sign;
     // the sine's sign is q's high bit, bit 31 of b.
     const uint32_t t = b ^ (b << 1);
-    const bool swap = (t & 0x40000000u) != 0u;
-    const float c = swap ? sn : cs;
-    const float s = swap ? cs : sn;
-    z0 = R * __uint_as_float(__float_as_uint(c) ^ (t & 0x80000000u));
-    z1 = R * __uint_as_float(__float_as_uint(s) ^ (b & 0x80000000u));
+    const uint32_t swap = (uint32_t)((int32_t)(t << 1) >> 31);      // all ones iff bit 30 of t
+    const uint32_t sb = __float_as_uint(sn), cb = __float_as_uint(cs);
+    const uint32_t c = __builtin_amdgcn_bitop3_b32(swap, sb, cb, 0xCA);  // swap ? sn : cs, bitwise
+    const uint32_t s = __builtin_amdgcn_bitop3_b32(swap, cb, sb, 0xCA);  // swap ? cs : sn
+    z0 = R * __uint_as_float(c ^ (t & 0x80000000u));
+    z1 = R * __uint_as_float(s ^ (b & 0x80000000u));
 }
 
 // Normals of the horizontal site pair (2a, y), (2a+1, y) at fine step m.
