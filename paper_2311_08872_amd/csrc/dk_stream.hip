@@ -46,6 +46,8 @@ struct Geo {
     static constexpr int NBS = EXT / 2;                       // 2x2 blocks per side
     static constexpr int NBLK = NBS * NBS;
     static constexpr int BPT = (NBLK + THREADS - 1) / THREADS;
+    static constexpr int NCELL = EXT * EXT;
+    static constexpr int CPT = (NCELL + THREADS - 1) / THREADS;   // cells per thread, row-major deal
 };
 
 __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
@@ -60,6 +62,7 @@ __global__ void __launch_bounds__(Geo<D>::THREADS, 4) stream_kernel(const Stream
 #pragma clang fp contract(off)
     constexpr int THREADS = Geo<D>::THREADS;
     constexpr int HH = Geo<D>::HH, EXT = Geo<D>::EXT, NBS = Geo<D>::NBS, NBLK = Geo<D>::NBLK, BPT = Geo<D>::BPT;
+    constexpr int NCELL = Geo<D>::NCELL, CPT = Geo<D>::CPT;
     constexpr bool FUSED = PAIR && D == 4;     // coarse step taken by this kernel
     constexpr bool SPLIT = PAIR && D != 4;     // noise sums kept in HBM, coarse step by its own kernel
     constexpr int HB = HH / 2;                 // first block of the tile interior
@@ -88,28 +91,35 @@ __global__ void __launch_bounds__(Geo<D>::THREADS, 4) stream_kernel(const Stream
     };
     auto interior = [&](int bx, int by) { return bx >= HB && bx < HB + CT && by >= HB && by < HB + CT; };
 
-    float cmp[BPT][4], Z[BPT][2];
+    // Two deals of the extended tile to the threads: 2x2 blocks (b = t + k THREADS) for the noise,
+    // whose generator calls cover horizontal site pairs and whose restriction sums 2x2 cells, and
+    // single cells in row-major order (i = t + k THREADS) for the update, so that the lanes of a
+    // wavefront read and write consecutive LDS words (no bank conflicts) and the halo's shrinking
+    // update region is shared out cell by cell.
+    float cmp[CPT], Z[BPT][2];
     // load the extended tile (and, continuing a group, the running noise sums)
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+        const int i = t + k * THREADS;
+        cmp[k] = 0.f;
+        if (i < NCELL) {
+            const int ex = i % EXT, ey = i / EXT;
+            const int gx = wrapi(tx0 + ex - HH, n), gy = wrapi(ty0 + ey - HH, n);
+            sr[i] = rin[(size_t)gy * n + gx];
+            cmp[k] = cin[(size_t)gy * n + gx];
+        }
+    }
 #pragma unroll
     for (int k = 0; k < BPT; ++k) {
         const int b = t + k * THREADS;
         Z[k][0] = 0.f;
         Z[k][1] = 0.f;
-        if (b < NBLK) {
+        if constexpr (SPLIT) {
             const int bx = b % NBS, by = b / NBS;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int ex = 2 * bx + (q & 1), ey = 2 * by + (q >> 1);
-                const int gx = wrapi(tx0 + ex - HH, n), gy = wrapi(ty0 + ey - HH, n);
-                sr[ey * EXT + ex] = rin[(size_t)gy * n + gx];
-                cmp[k][q] = cin[(size_t)gy * n + gx];
-            }
-            if constexpr (SPLIT) {
-                if (A.z_load && interior(bx, by)) {
-                    const float2 zz = *zslot(bx, by, 0);
-                    Z[k][0] = zz.x;
-                    Z[k][1] = zz.y;
-                }
+            if (b < NBLK && A.z_load && interior(bx, by)) {
+                const float2 zz = *zslot(bx, by, 0);
+                Z[k][0] = zz.x;
+                Z[k][1] = zz.y;
             }
         }
     }
@@ -179,61 +189,48 @@ __global__ void __launch_bounds__(Geo<D>::THREADS, 4) stream_kernel(const Stream
             }
         }
         __syncthreads();
-        // update region [j + 1, EXT - j - 1)
-        float nv[BPT][4];
+        // update region [j + 1, EXT - j - 1), one cell per deal slot
+        float nv[CPT];
 #pragma unroll
-        for (int k = 0; k < BPT; ++k) {
-            const int b = t + k * THREADS;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) nv[k][q] = 0.f;
-            if (b >= NBLK) continue;
-            const int bx = b % NBS, by = b / NBS;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int ex = 2 * bx + (q & 1), ey = 2 * by + (q >> 1);
-                if (ex <= j || ex >= EXT - j - 1 || ey <= j || ey >= EXT - j - 1) continue;
-                const int c = ey * EXT + ex;
-                const float rv = sr[c];
-                const float lap = fmaf(-4.0f, rv, (sr[c - 1] + sr[c + 1]) + (sr[c - EXT] + sr[c + EXT]));
-                float div;
-                if (FLUX == DK_FLUX_CENTRAL) div = (sf0[c + 1] - sf0[c - 1]) + (sf1[c + EXT] - sf1[c - EXT]);
-                else div = (sf0[c] - sf0[c - 1]) + (sf1[c] - sf1[c - EXT]);
-                const float d = fmaf(kappa, div, a * lap);
-                const float y = d - cmp[k][q];
-                const float tv = rv + y;
-                cmp[k][q] = (tv - rv) - y;
-                nv[k][q] = tv;
-            }
+        for (int k = 0; k < CPT; ++k) {
+            const int i = t + k * THREADS;
+            nv[k] = 0.f;
+            if (i >= NCELL) continue;
+            const int ex = i % EXT, ey = i / EXT;
+            if (ex <= j || ex >= EXT - j - 1 || ey <= j || ey >= EXT - j - 1) continue;
+            const int c = i;
+            const float rv = sr[c];
+            const float lap = fmaf(-4.0f, rv, (sr[c - 1] + sr[c + 1]) + (sr[c - EXT] + sr[c + EXT]));
+            float div;
+            if (FLUX == DK_FLUX_CENTRAL) div = (sf0[c + 1] - sf0[c - 1]) + (sf1[c + EXT] - sf1[c - EXT]);
+            else div = (sf0[c] - sf0[c - 1]) + (sf1[c] - sf1[c - EXT]);
+            const float d = fmaf(kappa, div, a * lap);
+            const float y = d - cmp[k];
+            const float tv = rv + y;
+            cmp[k] = (tv - rv) - y;
+            nv[k] = tv;
         }
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < BPT; ++k) {
-            const int b = t + k * THREADS;
-            if (b >= NBLK) continue;
-            const int bx = b % NBS, by = b / NBS;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int ex = 2 * bx + (q & 1), ey = 2 * by + (q >> 1);
-                if (ex <= j || ex >= EXT - j - 1 || ey <= j || ey >= EXT - j - 1) continue;
-                sr[ey * EXT + ex] = nv[k][q];
-            }
+        for (int k = 0; k < CPT; ++k) {
+            const int i = t + k * THREADS;
+            if (i >= NCELL) continue;
+            const int ex = i % EXT, ey = i / EXT;
+            if (ex <= j || ex >= EXT - j - 1 || ey <= j || ey >= EXT - j - 1) continue;
+            sr[i] = nv[k];
         }
         __syncthreads();
     }
     // write back the interior
 #pragma unroll
-    for (int k = 0; k < BPT; ++k) {
-        const int b = t + k * THREADS;
-        if (b >= NBLK) continue;
-        const int bx = b % NBS, by = b / NBS;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int ex = 2 * bx + (q & 1), ey = 2 * by + (q >> 1);
-            if (ex < HH || ex >= EXT - HH || ey < HH || ey >= EXT - HH) continue;
-            const size_t g = (size_t)(ty0 + ey - HH) * n + (tx0 + ex - HH);
-            rout[g] = sr[ey * EXT + ex];
-            cout[g] = cmp[k][q];
-        }
+    for (int k = 0; k < CPT; ++k) {
+        const int i = t + k * THREADS;
+        if (i >= NCELL) continue;
+        const int ex = i % EXT, ey = i / EXT;
+        if (ex < HH || ex >= EXT - HH || ey < HH || ey >= EXT - HH) continue;
+        const size_t g = (size_t)(ty0 + ey - HH) * n + (tx0 + ex - HH);
+        rout[g] = sr[i];
+        cout[g] = cmp[k];
     }
     if constexpr (FUSED) {
         if (!A.do_coarse) return;
