@@ -1,8 +1,10 @@
 """Build the gfx950 library ``libdk_mlmc.so`` in-tree with hipcc.
 
 Every HIP translation unit is compiled for gfx950 only, with packed-FP32 instructions
-disabled and with correctly rounded FP32 division and square root (the Gaussian transform
-relies on both being correctly rounded).
+disabled and with correctly rounded FP32 division and square root wherever the source writes
+them (the Gaussian transform's radius root is formed correctly rounded by its own sequence;
+the remaining FP32 roots and quotients, e.g. of the FP32 Fourier and semi-implicit kernels,
+take the compiler's correctly rounded ones).
 """
 import os
 import subprocess
