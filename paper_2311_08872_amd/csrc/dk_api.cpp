@@ -593,7 +593,7 @@ void save_tuning_cache(const dk_context* ctx)
 }
 
 // Tile-shape choice for the FP32 noisy kernels: a forced variant, a cached choice, or the
-// fastest variant on a short tuning batch (same tables, at most 256 fine steps, samples from
+// fastest variant on a short tuning batch (same tables, at most 2048 fine steps, samples from
 // the requested range; the outputs are discarded).  Small jobs use the default shape.
 int choose_shape(dk_context* ctx, const dk_problem* p, bool pair, const dk::LevelArgs& A, uint64_t count,
                  double cells_per_sample, hipStream_t s, int* variant)
@@ -614,13 +614,12 @@ int choose_shape(dk_context* ctx, const dk_problem* p, bool pair, const dk::Leve
     int nvar = 0;
     while (dk::shape_rows(nf, nvar) > 0) ++nvar;
     if (nvar < 2) { ctx->tuned[key] = 0; save_tuning_cache(ctx); return DK_OK; }
-    // The batch holds about eight rounds of blocks of the default shapes on 256 CUs (1024-lane
-    // blocks of one 128^2 pair, four 64^2 blocks per CU, 32768 samples of the smaller grids): with
-    // one or two rounds every CU starts its blocks in step and the ranking of the shapes differs
-    // from that of production launches; 256 steps suffice.
+    // The batch resembles a production launch: the level's own horizon (capped at 2048 steps;
+    // a much shorter one favours shapes whose per-sample setup is cheaper, not their time loop)
+    // and about one full round of blocks (256 CUs) of the larger grids.
     dk::LevelArgs T = A;
-    T.count = std::min<uint64_t>(count, nf <= 32 ? 32768 : (nf == 64 ? 8192 : 2048));
-    T.steps = std::min(A.steps, 256);
+    T.count = std::min<uint64_t>(count, nf <= 32 ? 8192 : (nf == 64 ? 1024 : 256));
+    T.steps = std::min(A.steps, 2048);
     T.field_f = nullptr;
     T.field_c = nullptr;
     int rc = ctx->per_sample.ensure(sizeof(double) * 2 * A.n_obs * T.count);
