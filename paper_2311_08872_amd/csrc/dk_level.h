@@ -486,8 +486,16 @@ __device__ __forceinline__ void level_body(const LevelArgs& A, uint64_t local0, 
                 for (int c = 0; c < CCc; ++c) { Z[i][c][0] = Real(0); Z[i][c][1] = Real(0); }
         }
     } else {
+        // grouped by four steps like the pairs' loop: the flat loop of single steps compiles to a
+        // schedule that runs 5 % slower on MI355X (same steps in the same order)
+        const int M4 = A.steps / 4;
 #pragma unroll 1
-        for (int m = 0; m < A.steps; ++m) fine_step(m);
+        for (int mq = 0; mq < M4; ++mq) {
+#pragma unroll 1
+            for (int j = 0; j < 4; ++j) fine_step(4 * mq + j);
+        }
+#pragma unroll 1
+        for (int m = 4 * M4; m < A.steps; ++m) fine_step(m);
     }
 
     double* dst = A.out + (size_t)(active ? local : 0) * A.n_obs * 2;
