@@ -64,7 +64,8 @@ __device__ __forceinline__ float sqrt_rn_normal(float x)
 
 // The sequence below is that definition written with integer bit operations where the
 // definition selects or negates (the same values, bit for bit, without lane-mask hazards):
-//   the fold:  m > binary32(1.41421356) iff the significand field of (float)w exceeds 0x3504f3;
+//   the fold:  m > binary32(1.41421356) = 0x1.6a09e6p+0 iff the frexp significand of (float)w,
+//              which is half of m, exceeds 0x1.6a09e6p-1 (its significand field exceeds 0x3504f3);
 //   the complement angle:  1 - f = (2 (j ^ 0x7fffff) + 1) 2^-24 exactly, and f > 1/2 iff bit 22 of j;
 //   the quadrant turn:  (c, s) -> (-s, c) twice folds into one swap and two sign-bit flips.
 __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& z0, float& z1)
