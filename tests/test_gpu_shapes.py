@@ -88,3 +88,29 @@ def test_tuning_choices_round_trip_through_json(tmp_path, monkeypatch, capfd):
     ctx3.load_tuning_json(text)
     assert json.loads(ctx3.tuning_json()) == j
     ctx3.close()
+
+
+def test_tuning_json_samples_per_block_entries():
+    """A shape entry may name its samples per block: an existing (rows, spw) pair selects that
+    variant, one that no compiled shape has is rejected, and an entry without spw names the
+    ~256-lane shape with that row count."""
+    import json
+    n = 64
+    wide = [v for v in range(4) if dk.Context.shape_rows(n, v) == 8 and dk.Context.shape_spw(n, v) == 4]
+    assert wide, "the 64^2 kernel has a 1024-lane 8-row shape"
+    assert dk.Context.shape_spw(n, 0) == 1 and dk.Context.shape_rows(n, 0) == 8
+
+    def doc(entry):
+        return json.dumps({"format": "dk-tile-shapes-1", "arch": arch, "shapes": [entry]})
+
+    ctx = dk.Context(0)
+    arch = json.loads(ctx.tuning_json())["arch"]
+    ctx.load_tuning_json(doc({"n": n, "pair": 1, "flux": 0, "rows": 8, "spw": 4}))
+    got = json.loads(ctx.tuning_json())["shapes"]
+    assert {"n": n, "pair": 1, "flux": 0, "rows": 8, "spw": 4} in got
+    ctx.load_tuning_json(doc({"n": n, "pair": 1, "flux": 0, "rows": 8}))
+    got = json.loads(ctx.tuning_json())["shapes"]
+    assert {"n": n, "pair": 1, "flux": 0, "rows": 8, "spw": 1} in got
+    with pytest.raises(dk.DKError):
+        ctx.load_tuning_json(doc({"n": n, "pair": 1, "flux": 0, "rows": 8, "spw": 3}))
+    ctx.close()
