@@ -1,10 +1,15 @@
 #!/usr/bin/env python3
-"""Benchmark: wall time of plain MLMC to RMSE 1e-3 on the config-2 workload, on one MI355X.
+"""Benchmark: wall time of plain MLMC at eps = 1e-3 on the config-2 workload, on one MI355X.
 
 One step = one complete run of Algorithm 1 (dk_mlmc_estimate) from a fresh context: level
 setup and discrete mean field on the device, then rounds of batched level pairs (Philox +
 Box--Muller noise, fused fine/coarse EM stepping, observables, ordered FP64 moment sums)
-until the bias test passes.  Each step uses its own seed.
+until the bias test passes or the finest level is reached with the variance target eps^2/2
+met.  Each step uses its own seed.  One step takes minutes, so the loop is wall-budgeted:
+warm-ups (at a loose eps) stop once --warmup-budget seconds are spent, and a further timed
+step starts only while the time since start plus the longest step so far stays within
+--time-budget; "steps" reports the steps actually timed, "steps_requested" the request.  A
+step is never cut short.
 
 Workload (synthetic, defined by formulas): unit torus, levels h = 1/8 .. 1/128,
 tau_l = 0.1 h_l^2, T = 0.05, rho0 = 1 + 0.5 cos 2 pi x cos 2 pi y, N = 1e4, primary observable
@@ -21,16 +26,19 @@ import os
 import sys
 import time
 
+T_START = time.perf_counter()
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "MLMC wall-time to RMSE 1e-3 (plain vs learned CV); cell-updates/s and HBM %"
 
-# Algorithmic vector-ALU operations per fine cell update of a coupled pair: half a
+# Algorithmic vector-ALU operations per FINE cell update of a coupled pair: half a
 # Philox4x32-10 call (40), one binary32 Box--Muller pair (60), the explicit EM update with
 # central flux and compensated increment (18), the NN restriction and the amortised coarse
-# step (3).
+# step (3).  The coarse step is included here, so the count it multiplies is fine updates only
+# (the library's per-level statistics count a pair's coarse updates too, 1/16 of the fine ones).
 OPS_PER_CELL_UPDATE = 121.0
+COARSE_SHARE = 1.0 / 16.0
 # MI355X vector FP32 rate: 157.3 TFLOP/s counts an FMA as 2 flops, i.e. 78.6e12 32-bit
 # vector lane-operations per second (256 CUs x 128 lanes x 2.4 GHz).
 VALU_PEAK_OPS = 256 * 128 * 2.4e9
@@ -62,6 +70,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--eps", type=float, default=1e-3)
     ap.add_argument("--warmup-eps", type=float, default=1e-2, help="accuracy of the untimed warmup runs")
+    ap.add_argument("--warmup-budget", type=float, default=30.0,
+                    help="no further warmup run starts after this many seconds of warmups")
+    ap.add_argument("--time-budget", type=float, default=450.0,
+                    help="a further timed step starts only if the seconds since start plus the longest "
+                         "step so far stay within this budget (the first timed step always runs)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle sampling")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -158,20 +171,35 @@ def main():
         p = base.with_(seed=seed)
         return dk.estimate(p, eps, ctx=ctx, level_moments=True)
 
+    warmups = 0
+    t_w = time.perf_counter()
     for w in range(args.warmup):
+        if w > 0 and time.perf_counter() - t_w > args.warmup_budget:
+            break
         ctx = dk.Context(0)
         one(1000 + w, ctx, args.warmup_eps)
         ctx.close()
+        warmups += 1
+    print(f"[bench] {warmups} warmup run(s) at eps={args.warmup_eps:g}: {time.perf_counter() - t_w:.1f} s",
+          file=sys.stderr, flush=True)
 
     torch.cuda.synchronize()
     results = []
+    step_s = []
     stats = {}
     t0 = time.perf_counter()
     for k in range(args.steps):
+        if k > 0 and (time.perf_counter() - T_START) + max(step_s) > args.time_budget:
+            print(f"[bench] stopping after {k} timed step(s): another ({max(step_s):.0f} s) would end past the "
+                  f"{args.time_budget:.0f} s budget", file=sys.stderr, flush=True)
+            break
+        ts = time.perf_counter()
         ctx = dk.Context(0)            # fresh context: level tables and mean field are rebuilt
         r = one(k, ctx, args.eps)
-        print(f"[bench] step {k}: {time.perf_counter() - t0:.1f} s, L={r['L']} M={r['M']}", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
+        step_s.append(time.perf_counter() - ts)
+        print(f"[bench] step {k}: {step_s[-1]:.1f} s, L={r['L']} M={r['M']} converged={r['converged']} "
+              f"rmse_est={r['rmse_est']:.3g}", file=sys.stderr, flush=True)
         for s in ctx.stats():
             key = (s["level"], s["coupled"])
             acc = stats.setdefault(key, {"launches": 0, "samples": 0, "kernel_ms": 0.0, "cell_updates": 0.0})
@@ -182,7 +210,8 @@ def main():
         results.append(r)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    per_step = wall / args.steps
+    steps = len(results)
+    per_step = wall / steps
 
     cells = sum(r["cell_updates"] for r in results)
     kernel_ms = sum(v["kernel_ms"] for v in stats.values())
@@ -191,7 +220,8 @@ def main():
     traffic = None
     if (TRAFFIC["sha256"] and TRAFFIC["sha256"] == kernel_source_sha256() and (dl, dc) == (base.levels - 1, True)):
         traffic = TRAFFIC["fetch_bytes_per_dispatch"] + TRAFFIC["write_bytes_per_pair"] * dom["samples"] / dom["launches"]
-    ops_per_launch = OPS_PER_CELL_UPDATE * dom["cell_updates"] / dom["launches"]
+    fine_per_launch = dom["cell_updates"] / dom["launches"] / (1.0 + COARSE_SHARE if dc else 1.0)
+    ops_per_launch = OPS_PER_CELL_UPDATE * fine_per_launch
     achieved = ops_per_launch / avg_launch_s
     last = results[-1]
     # plain MC on the finest level reached: M_MC = 2 Var(P_L) / eps^2, time from the measured
@@ -207,8 +237,10 @@ def main():
         "value": per_step,
         "unit": "s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "steps_requested": args.steps,
+        "warmup": warmups,
+        "warmup_requested": args.warmup,
         "ms_per_step": per_step * 1e3,
         "higher_is_better": False,
         "scaling": "weak",
@@ -219,7 +251,13 @@ def main():
                                "rho0=1+0.5cos2pix cos2piy, N=1e4, psi=x^2 of the centred sqrt(N)-scaled "
                                "<rho_T, sin2pix+sin2piy>, Algorithm 1, eps=1e-3",
                    "eps": args.eps, "levels": base.levels, "N": base.N, "state": "fp32 (compensated)",
-                   "seeds": list(range(args.steps))},
+                   "seeds": list(range(steps))},
+        "reached": {"converged": last["converged"], "rmse_est": last["rmse_est"], "bias_est": last["bias_est"],
+                    "var_est": last["var_est"][base.primary], "eps": args.eps,
+                    "value_is": ("wall time of Algorithm 1 to RMSE eps (bias test passed)" if last["converged"] else
+                                 "wall time of Algorithm 1 to the variance target eps^2/2 on the finest level "
+                                 f"allowed (L={last['L']}); the bias test was not passed, so the estimated RMSE "
+                                 f"is {last['rmse_est']:.3g}, not eps")},
         "cell_updates_per_s": cells / wall,
         "kernel_fraction_of_wall": kernel_ms / 1e3 / wall,
         "mlmc": {"L": last["L"], "converged": last["converged"], "M": last["M"],
@@ -232,10 +270,11 @@ def main():
                      "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12, "unit": "Top/s",
                      "frac": achieved / VALU_PEAK_OPS, "traffic": traffic,
                      "traffic_unit": "bytes per launch (HBM, rocprofv3 counters)",
-                     "ops_per_cell_update": OPS_PER_CELL_UPDATE,
-                     "cell_updates_per_launch": dom["cell_updates"] / dom["launches"],
+                     "ops_per_fine_cell_update": OPS_PER_CELL_UPDATE,
+                     "fine_cell_updates_per_launch": fine_per_launch,
                      "avg_launch_ms": avg_launch_s * 1e3,
-                     "kernel_cell_updates_per_s": dom["cell_updates"] / (dom["kernel_ms"] / 1e3)},
+                     "launches": dom["launches"],
+                     "fine_cell_updates_per_s": fine_per_launch / avg_launch_s},
         "kernels": {f"L{l}{'p' if c else 's'}": v for (l, c), v in sorted(stats.items())},
     }
     if not args.no_cpu:
