@@ -43,14 +43,15 @@ COARSE_SHARE = 1.0 / 16.0
 # vector lane-operations per second (256 CUs x 128 lanes x 2.4 GHz).
 VALU_PEAK_OPS = 256 * 128 * 2.4e9
 
-# HBM traffic of the dominant kernel (the 128^2 pair level kernel), from rocprofv3 --pmc
-# FETCH_SIZE and WRITE_SIZE runs of `bench.py --eps 2e-3` (the same kernel at the same full launch
-# size), scaled by what the counters read for a 256 MiB copy (fetch x2.0, write x1.0): a constant
-# per dispatch (the level tables, missed once per XCD) plus bytes per pair (the outputs).  It is
+# HBM traffic of the dominant kernel (the 128^2 pair level kernel), from rocprofv3 --pmc runs of
+# `bench.py --workload counters` (one production launch of 14024 pairs): read bytes from the
+# size-resolved request counters (32/64/128-B requests to EA), written bytes from WRITE_SIZE; both
+# read 1.000 x the bytes of a 256 MiB copy (FETCH_SIZE reads 0.5 x on gfx950).  A constant per
+# dispatch (the level tables, fetched once per compute die) plus bytes per pair (the outputs).  It is
 # reported only while the kernel sources hash to the value the counters were taken on.
-TRAFFIC = {"sha256": "eb72a2150828a5a51d38e2b858f85e9bc73b28f0f74cf53a9961341d019c57b1",
-           "fetch_bytes_per_dispatch": 1719.5 * 1024 * 2.0, "write_bytes_per_pair": 32.0 * 1.0,
-           "profile": "profiles/level_kernel_128_pair_hbm_counters.md"}
+TRAFFIC = {"sha256": "35f31741fafd7578606a81ddfbdfcae17d29bb276403315e97cf4186ba5a601b",
+           "read_bytes_per_dispatch": 3320.5 * 1024, "write_bytes_per_pair": 32.0,
+           "profile": "profiles/level_kernel_128_pair_counters_workload_hbm.md"}
 KERNEL_SOURCES = ["dk_level.h", "dk_rng.h", "dk_kernels.hip", "dk_internal.h"]
 
 
@@ -81,7 +82,7 @@ def parse():
                     help="only copy a 256 MiB buffer 4 times (reference for HBM byte counters)")
     ap.add_argument("--workload", default="config2",
                     choices=["config2", "config2-mc", "config3", "config4", "config5", "paper-type1", "paper-type2",
-                             "paper-couplings", "paper-theta"],
+                             "paper-couplings", "paper-theta", "counters"],
                     help="config2 (default): the bench line; the others print a report line: config2-mc "
                          "plain Monte Carlo on the finest config-2 level to the same eps, config3 "
                          "low-density MLMC with persistent rounds, config4 learned control variate, "
@@ -89,7 +90,8 @@ def parse():
                          "Type-1 experiment (MLMC and MC at its accuracies, speed-ups against its table), "
                          "paper-type2 its variance-reduction factor against h_min, paper-couplings the "
                          "symmetric NN and the Fourier coupling against the NN coupling, paper-theta "
-                         "explicit against Crank-Nicolson and implicit Euler time stepping")
+                         "explicit against Crank-Nicolson and implicit Euler time stepping, counters one "
+                         "production-size launch of each hot kernel and a 256 MiB copy (for rocprofv3 --pmc runs)")
     ap.add_argument("--N", type=float, default=None, help="particle number (config3: 1e5, config5: 1e6)")
     ap.add_argument("--samples", type=int, default=32, help="config5: finest-level pairs to time")
     ap.add_argument("--depth-only", action="store_true",
@@ -163,7 +165,8 @@ def main():
     if args.workload != "config2":
         {"config2-mc": bench_config2_mc, "config3": bench_config3, "config4": bench_config4,
          "config5": bench_config5, "paper-type1": bench_paper_type1,
-         "paper-type2": bench_paper_type2, "paper-couplings": bench_paper_couplings, "paper-theta": bench_paper_theta}[args.workload](args)
+         "paper-type2": bench_paper_type2, "paper-couplings": bench_paper_couplings, "paper-theta": bench_paper_theta,
+         "counters": bench_counters}[args.workload](args)
         return
     base = W.config2(N=1e4)
 
@@ -219,7 +222,7 @@ def main():
     avg_launch_s = dom["kernel_ms"] / 1e3 / dom["launches"]
     traffic = None
     if (TRAFFIC["sha256"] and TRAFFIC["sha256"] == kernel_source_sha256() and (dl, dc) == (base.levels - 1, True)):
-        traffic = TRAFFIC["fetch_bytes_per_dispatch"] + TRAFFIC["write_bytes_per_pair"] * dom["samples"] / dom["launches"]
+        traffic = TRAFFIC["read_bytes_per_dispatch"] + TRAFFIC["write_bytes_per_pair"] * dom["samples"] / dom["launches"]
     fine_per_launch = dom["cell_updates"] / dom["launches"] / (1.0 + COARSE_SHARE if dc else 1.0)
     ops_per_launch = OPS_PER_CELL_UPDATE * fine_per_launch
     achieved = ops_per_launch / avg_launch_s
@@ -732,6 +735,62 @@ def bench_config5(args):
     _report(f"config-5 throughput: coupled pairs at 256^2, 512^2, 1024^2 (N={N:g}, tau=0.1h^2, "
             f"{args.samples} pairs at 1024^2), streaming kernel", fin["cell_updates_per_s"], "cell updates/s",
             {"grids": out, "depths_1024": depths, "noise_free_stencil": heat})
+
+def bench_counters(args):
+    """One launch of each hot kernel at the size it runs in production, for HBM byte counters
+    (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE / request sizes, one pass per counter set):
+      1. a 256 MiB device copy, twice (the calibration: 256 MiB read and 256 MiB written per launch);
+      2. the noise-free FP32 stencil (heat_f32_kernel), 8 steps at 256^2 x 4096 and at 1024^2 x 256
+         (one launch per step: 1 GiB read and 1 GiB written algorithmically);
+      3. the streaming kernel on 4 pairs and 4 single paths of the 1024^2 / 512^2 pair over 128 fine
+         steps at each depth D = 1, 2, 4, 8;
+      4. the resident 128^2 pair kernel: one launch of 14024 pairs (the production chunk of the
+         config-2 finest level, 8192 fine steps, about 3.3 s).
+    Prints one report line with the HIP-event kernel times."""
+    import torch
+    import dk_workloads as W
+    import paper_2311_08872_amd as dk
+    out = {}
+    src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    ctx = dk.Context(0)
+    heat = {}
+    for n, batch in ((256, 4096), (1024, 256)):
+        x = torch.ones((batch, n, n), dtype=torch.float32, device="cuda")
+        ms = dk.heat_steps(x, 8, 0.1, ctx=ctx)
+        heat[str(n)] = {"batch": batch, "steps": 8, "kernel_ms": ms, "GB_per_s": 8.0 * batch * n * n * 8 / (ms / 1e3) / 1e9}
+        del x
+    out["heat_f32"] = heat
+    p = W.config5(N=1e6)
+    ps = p.with_(n0=512, levels=2)
+    ps = ps.with_(T=ps.tau(1) * 128, steps_policy=W.STEPS_EXACT)
+    st = {}
+    for coupled in (True, False):
+        for d in (1, 2, 4, 8):
+            ctx.set_stream_depth(d)
+            ctx.reset()
+            (dk.level_pair if coupled else dk.mc_level)(ps, 1, 0, 4, ctx=ctx)
+            torch.cuda.synchronize()
+            s_ = [s for s in ctx.stats() if s["level"] == 1][0]
+            st[f"{'pair' if coupled else 'single'}_D{d}"] = {"kernel_ms": s_["kernel_ms"], "cell_updates": s_["cell_updates"]}
+    ctx.set_stream_depth(0)
+    out["stream_1024"] = st
+    c2 = W.config2(N=1e4)
+    ctx.set_shape(128, 0)
+    ctx.reset()
+    dk.level_pair(c2, 4, 0, 14024, ctx=ctx)
+    torch.cuda.synchronize()
+    s_ = [s for s in ctx.stats() if s["level"] == 4][0]
+    out["level_128_pair"] = {"pairs": 14024, "launches": s_["launches"], "kernel_ms": s_["kernel_ms"],
+                             "fine_cell_updates_per_s": s_["cell_updates"] / (1 + 1 / 16) / (s_["kernel_ms"] / 1e3)}
+    ctx.close()
+    _report("one production-size launch of each hot kernel (copy calibration, heat_f32, stream, 128^2 pair)",
+            out["level_128_pair"]["fine_cell_updates_per_s"], "fine cell updates/s (128^2 pair launch)", out)
+
 
 if __name__ == "__main__":
     main()
