@@ -231,7 +231,7 @@ def main():
     # per-sample kernel cost of that level (projected, as the paper did for its smallest eps)
     Lr = last["L"]
     lm = last["level_moments"][Lr][base.primary]
-    varPL = max(0.0, (lm.sums[3] - lm.sums[2] ** 2 / lm.count) / (lm.count - 1))
+    varPL = lm.stats(1)[1]
     pair_stat = stats.get((Lr, True))
     mc_sample_s = (pair_stat["kernel_ms"] / 1e3 / pair_stat["samples"]) / (1 + 1 / 16) if pair_stat else float("nan")
     mc_M = math.ceil(2 * varPL / args.eps ** 2)
@@ -530,10 +530,10 @@ def bench_paper_type2(args):
             for l in range(L + 1):
                 m = mom[l][p.primary]
                 n = m.count
-                V.append(max(0.0, (m.sums[1] - m.sums[0] ** 2 / n) / (n - 1)))
+                V.append(m.var)
                 C.append(p.n(l) ** 2 * p.steps(l) * (1.0 + (l > 0) / 16.0))
             mL = mom[L][p.primary]
-            var_PL = max(0.0, (mL.sums[3] - mL.sums[2] ** 2 / mL.count) / (mL.count - 1))
+            var_PL = mL.stats(1)[1]
             var_ml = sum(V[l] / count[l] for l in range(L + 1))
             cost = sum(count[l] * C[l] for l in range(L + 1))
             c_single = p.n(L) ** 2 * p.steps(L)
@@ -578,10 +578,10 @@ def bench_config3(args):
         Y, V = [], []
         for l in range(L + 1):
             m = prof[l][p.primary]
-            Y.append(m.sums[0] / m.count)
-            V.append(max(0.0, (m.sums[1] - m.sums[0] ** 2 / m.count) / (m.count - 1)))
+            Y.append(m.mean)
+            V.append(m.var)
         pilot = dk.round_sums(p, 0, [0], [1000], tag=W.TAG_MC, round_mode=3, ctx=ctx)[0][p.primary]
-        scale = abs(pilot.sums[2] / pilot.count)
+        scale = abs(pilot.stats(1)[0])
         eps = rel * scale
         ctx.close()
         ctx = dk.Context(0)

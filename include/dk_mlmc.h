@@ -169,6 +169,12 @@ typedef struct {
     double comp[DK_NMOM];
 } dk_moments;
 
+/* Sample mean and unbiased sample variance (denominator count - 1; 0 when count = 1) of one
+ * quantity of a moment record, from its compensated sums: q = 0 for Y = P_fine - P_coarse, 1 for
+ * P_fine, 2 for P_coarse (the estimates of eq. (MLMCEstimator) and the V_l of eq. (opt_M_ell)).
+ * Host arithmetic only.  DK_EINVAL for NULL pointers, q outside 0..2 or a record without samples. */
+int dk_moments_mean_var(const dk_moments* m, int32_t q, double* mean, double* var);
+
 typedef struct {
     int32_t m_pilot;          /* pilot samples per level (Algorithm 1's M-bar); default 1000     */
     int32_t L_start;          /* first L (default 2)                                             */

@@ -76,15 +76,24 @@ class Moments:
     count: int
     sums: np.ndarray   # [DK_NMOM]: Y, Y^2, Pf, Pf^2, Pc, Pc^2 (compensated values)
 
+    def stats(self, q: int = 0):
+        """(mean, unbiased variance) of Y (q = 0), P_fine (1) or P_coarse (2): dk_moments_mean_var."""
+        m = L.dk_moments()
+        m.count = self.count
+        for k in range(L.DK_NMOM):
+            m.sum[k] = float(self.sums[k])
+            m.comp[k] = 0.0
+        mean, var = C.c_double(), C.c_double()
+        _check(L.load().dk_moments_mean_var(C.byref(m), q, C.byref(mean), C.byref(var)))
+        return mean.value, var.value
+
     @property
     def mean(self) -> float:
-        return self.sums[0] / self.count
+        return self.stats(0)[0]
 
     @property
     def var(self) -> float:
-        n = self.count
-        m = self.sums[0] / n
-        return max(0.0, (self.sums[1] - n * m * m) / (n - 1)) if n > 1 else 0.0
+        return self.stats(0)[1]
 
 
 def _moments(arr) -> List[Moments]:

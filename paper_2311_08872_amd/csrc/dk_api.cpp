@@ -2330,6 +2330,19 @@ int dk_context_set_stream_depth(dk_context* ctx, int32_t depth)
     return DK_OK;
 }
 
+int dk_moments_mean_var(const dk_moments* m, int32_t q, double* mean, double* var)
+{
+    if (!m || !mean || !var) return fail(DK_EINVAL, "NULL argument");
+    if (q < 0 || q > 2) return fail(DK_EINVAL, "quantity %d outside 0..2 (Y, P_fine, P_coarse)", q);
+    if (m->count == 0) return fail(DK_EINVAL, "no samples");
+    const int k1 = q == 0 ? DK_MOM_Y : (q == 1 ? DK_MOM_PF : DK_MOM_PC);
+    const double n = (double)m->count;
+    const double mu = mom_value(*m, k1) / n;
+    *mean = mu;
+    *var = m->count > 1 ? std::max(0.0, (mom_value(*m, k1 + 1) - n * mu * mu) / (n - 1.0)) : 0.0;
+    return DK_OK;
+}
+
 int dk_mlmc_level_pair(dk_context* ctx, const dk_problem* problem, int32_t level, uint64_t first_sample,
                        uint64_t n_samples, uint32_t stream_tag, dk_moments* sums_out, double* per_sample_out, void* stream)
 {

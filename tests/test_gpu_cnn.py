@@ -1,8 +1,15 @@
 """GPU checks of the control-variate network kernels (BF16 MFMA, FP32 accumulation) against
 the FP64 reference network, and of the control-variate estimator's unbiasedness.
 
-Tolerances: the two 16->16 convolutions use BF16 operands (8 significant bits), so the forward
-output is compared at 3e-2 of the output RMS and each gradient block at 6e-2 relative norm.
+Tolerances.  The two 16->16 convolutions take BF16 operands (8 significant bits: each rounding
+is at most 2^-9 = 2e-3 relative) and accumulate in FP32; the first convolution, pooling and MLP
+run in FP32.  One rounding of each operand and of each layer's output gives at most
+3 x 2^-9 = 5.9e-3 relative per 16->16 layer on every product, and the two layers' errors add
+in the output; the sums over 144 products cancel only partly for these random weights and inputs
+(both layers' terms have one sign after the ReLU in about half of them), so the forward output is
+held to 1e-2 of its RMS (the bar of the scope's CNN parity item; measured 2.2e-3 .. 3.7e-3).  The
+backward pass runs the same BF16 products twice more (input gradients and weight gradients), so
+each gradient block is held to 3e-2 of its norm (measured 4.5e-3 .. 1.5e-2) and the loss to 1e-2.
 """
 import math
 
@@ -43,7 +50,8 @@ def test_forward_matches_fp64_reference(n, batch):
     r = dk.cnn_forward(p, torch.from_numpy(x).cuda()).cpu().numpy()
     rr = ref.forward(ref.unflatten(p.astype(np.float64)), x.astype(np.float64))
     rms = np.sqrt(np.mean(rr ** 2))
-    assert np.max(np.abs(r - rr)) <= 3e-2 * rms, (np.max(np.abs(r - rr)), rms)
+    banner(f"forward max error / RMS = {np.max(np.abs(r - rr)) / rms:.3g}")
+    assert np.max(np.abs(r - rr)) <= 1e-2 * rms, (np.max(np.abs(r - rr)), rms)
 
 
 @pytest.mark.parametrize("n,batch", [(16, 48), (32, 16)])
@@ -55,12 +63,15 @@ def test_gradient_matches_fp64_reference(n, batch):
     y = rng.standard_normal(batch).astype(np.float32)
     loss, g = dk.cnn_loss_grad(p, torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda())
     lr_, gr = ref.loss_and_grad(ref.unflatten(p.astype(np.float64)), x.astype(np.float64), y.astype(np.float64))
-    assert abs(loss - lr_) <= 3e-2 * lr_
+    assert abs(loss - lr_) <= 1e-2 * lr_
     gd = ref.unflatten(g.astype(np.float64))
+    worst = 0.0
     for k in ref.ORDER:
         num = np.linalg.norm(gd[k] - gr[k])
         den = np.linalg.norm(gr[k])
-        assert num <= 6e-2 * den + 1e-7, (k, num / max(den, 1e-30))
+        worst = max(worst, num / max(den, 1e-30))
+        assert num <= 3e-2 * den + 1e-7, (k, num / max(den, 1e-30))
+    banner(f"loss relative error {abs(loss - lr_) / lr_:.3g}; largest gradient-block relative error {worst:.3g}")
 
 
 def test_training_reduces_loss_and_keeps_estimator_unbiased():

@@ -33,6 +33,11 @@ def scaled_err(gpu: np.ndarray, ref: np.ndarray) -> float:
     return float(np.max(np.abs(gpu - ref) / np.maximum(np.maximum(np.abs(ref), rms), 1e-300)))
 
 
+def scaled_err_each(gpu: np.ndarray, ref: np.ndarray) -> np.ndarray:
+    rms = np.sqrt(np.mean(ref ** 2, axis=0, keepdims=True))
+    return np.abs(gpu - ref) / np.maximum(np.maximum(np.abs(ref), rms), 1e-300)
+
+
 def banner(msg):
     print(f"[gpu] {msg}", flush=True)
 
@@ -61,9 +66,10 @@ def test_meanfield_centring_constants():
 
 
 @pytest.mark.parametrize("make,N", [(W.paper_reg, 2e5), (W.paper_reg, 2e9), (W.paper_irreg, 2e9)])
-@pytest.mark.parametrize("level,count", [(0, 300), (1, 200), (2, 100), (3, 40), (4, 8)])
+@pytest.mark.parametrize("level,count", [(0, 300), (1, 200), (2, 100), (3, 40), (4, 8), (5, 8)])
 def test_paper_setting_per_sample_parity(make, N, level, count):
-    """The paper's Sec. 7 hierarchy from 4 x 4 (2 lanes per sample, 4 rows each) up to 64 x 64,
+    """The paper's Sec. 7 hierarchy from 4 x 4 (2 lanes per sample, 4 rows each) up to 128 x 128
+    (the finest pair of its Type-2 experiment, 1024 fine steps),
     both initial data, with its FP64 state: per-sample observables against the oracle, and the
     centring constants.  Bound, from the arithmetic: before centring, X sums terms of size
     sqrt(N) h^2 sum|rho phi| (4.5e4 x 2 at N = 2e9); each FP64 rounding of them is u = 1.1e-16
@@ -104,25 +110,77 @@ def test_config2_per_sample_parity(level, count):
 
 def test_config2_finest_pair_sampled():
     """The finest pair of config 2 (128^2 / 64^2, 8192 fine steps) in the launch shape the
-    benchmark uses: a batch of 512 pairs, of which 4 spread-out samples are recomputed."""
+    benchmark uses: a batch of 512 pairs, of which 16 spread-out samples are recomputed by the
+    oracle; errors scaled by the oracle's RMS over those 16."""
     p = W.config2(N=1e4)
     level = 4
-    banner("config2 finest pair, 512 samples, 4 checked")
+    banner("config2 finest pair, 512 samples, 16 checked")
     _, ps = dk.level_pair(p, level, 1000, 512, per_sample=True)
     torch.cuda.synchronize()
     gpu = ps.cpu().numpy()
     op = oracle.OracleProblem(p)
-    idx = [0, 171, 342, 511]
+    idx = [int(i) for i in np.linspace(0, 511, 16).round()]
     from concurrent.futures import ThreadPoolExecutor
-    with ThreadPoolExecutor(4) as ex:
+    with ThreadPoolExecutor(oracle.default_threads()) as ex:
         refs = list(ex.map(lambda i: oracle.run_pair(op, level, 1000 + i), idx))
     ref = np.stack(refs)
-    allg = gpu[idx]
-    # scale by the batch RMS of the GPU values (the oracle is only run on 4 samples)
-    rms = np.sqrt(np.mean(gpu ** 2, axis=0, keepdims=True))
-    err = np.max(np.abs(allg - ref) / np.maximum(np.abs(ref), rms))
+    err = scaled_err(gpu[idx], ref)
     banner(f"scaled FP32-vs-FP64 error {err:.3g} (tolerance {TOL:g})")
     assert err <= TOL, err
+
+
+@pytest.mark.parametrize("level,count", [(0, 120), (1, 60)])
+def test_config3_low_density_per_sample_parity(level, count):
+    """Config 3 at N = 1e3 on the levels where its sample paths are well conditioned (8^2 and 16^2:
+    N h^2 min(rho0) = 0.78 and 0.2 particles per cell at the datum's floor) with all 29 observables
+    (28 Fourier parts, uncentred, and the squared bump), per sample against the oracle."""
+    p = W.config3(N=1e3)
+    banner(f"config3 N=1e3 level={level} count={count} (nf={p.n(level)}, steps={p.steps(level)}, 29 observables)")
+    _, ps = dk.level_pair(p, level, 3, count, per_sample=True)
+    torch.cuda.synchronize()
+    gpu = ps.cpu().numpy()
+    ref = oracle.run_range(oracle.OracleProblem(p), level, 3, count)
+    assert gpu.shape == ref.shape == (count, 29, 2)
+    err = scaled_err(gpu.reshape(count, -1), ref.reshape(count, -1))
+    banner(f"scaled FP32-vs-FP64 error {err:.3g} (tolerance {TOL:g})")
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("level,count", [(2, 200), (3, 64), (4, 16)])
+def test_config3_low_density_estimator_parity(level, count):
+    """Config 3 at N = 1e3 on the resident levels where its sample paths are ill conditioned
+    (32^2 .. 128^2: N h^2 min(rho0) = 4.9e-2 .. 3.1e-3 particles per cell): sqrt([rho]^+) has an
+    unbounded derivative at 0 and these paths cross 0 often, so a rounding-size change of the state
+    grows to O(1) of a sample's value (the oracle's own values move by up to 0.33 of their RMS on
+    64^2 when its input moves by 1e-15, test_oracle_conditioning.py).  Per-sample agreement is
+    then not defined at any precision; the bar is the estimator's (the FP32 path's mean within the
+    statistical error of the FP64 oracle's), for P_fine, P_coarse and Y of all 29 observables:
+    |mean(gpu - oracle)| <= SE(oracle mean), and no bias: |mean(gpu - oracle)| <= 4.5 SE of the
+    paired differences + 1e-5 RMS."""
+    p = W.config3(N=1e3)
+    banner(f"config3 N=1e3 level={level} count={count} (nf={p.n(level)}, steps={p.steps(level)}, 29 observables)")
+    _, ps = dk.level_pair(p, level, 3, count, per_sample=True)
+    torch.cuda.synchronize()
+    gpu = ps.cpu().numpy()
+    ref = oracle.run_range(oracle.OracleProblem(p), level, 3, count)
+    assert gpu.shape == ref.shape == (count, 29, 2)
+    close = float(np.mean(scaled_err_each(gpu.reshape(count, -1), ref.reshape(count, -1)) <= TOL))
+    worst = 0.0
+    for j in range(29):
+        for q_gpu, q_ref in ((gpu[:, j, 0], ref[:, j, 0]), (gpu[:, j, 1], ref[:, j, 1]),
+                             (gpu[:, j, 0] - gpu[:, j, 1], ref[:, j, 0] - ref[:, j, 1])):
+            rms = math.sqrt(float(np.mean(q_ref ** 2)))
+            if rms == 0.0:
+                assert np.all(q_gpu == 0.0)
+                continue
+            d = q_gpu - q_ref
+            md = float(d.mean())
+            se_est = float(q_ref.std(ddof=1)) / math.sqrt(count)
+            se_pair = float(d.std(ddof=1)) / math.sqrt(count)
+            assert abs(md) <= se_est, (j, md, se_est)
+            assert abs(md) <= 4.5 * se_pair + 1e-5 * rms, (j, md, se_pair)
+            worst = max(worst, abs(md) / se_est)
+    banner(f"{100 * close:.1f} % of values within {TOL:g}; largest |mean difference| / SE = {worst:.3g}")
 
 
 @pytest.mark.parametrize("flux", [W.FLUX_CENTRAL, W.FLUX_STAGGERED])

@@ -1,6 +1,7 @@
 """Algorithm 1 with each round's levels run concurrently (one stream per level) or captured into
 a hipGraph launched once per round gives exactly the results of the level-by-level run: the
 samples, their chunking and the ordered sums are the same."""
+import numpy as np
 import pytest
 
 import dk_workloads as W
@@ -172,3 +173,47 @@ def test_measured_cost_model():
     assert c[-1] / c[0] > 100, c
     se = math.sqrt(cells["var_est"][0] + meas["var_est"][0])
     assert abs(cells["estimate"][0] - meas["estimate"][0]) < 4.5 * se
+
+
+def _moment_values(pf, pc):
+    y = pf - pc
+    return [y, y * y, pf, pf * pf, pc, pc * pc]
+
+
+@pytest.mark.parametrize("name,problem,first,count", [
+    ("config2", W.config2(N=1e4).with_(seed=31), [7, 0, 3, 11, 2], [300, 120, 40, 12, 3]),
+    # 29 observables; N = 1e5, where the sample paths are well conditioned on every level (at N = 1e3
+    # they are not from 32^2 on, and per-sample agreement is undefined; test_gpu_parity.py)
+    ("config3", W.config3(N=1e5).with_(levels=5, seed=32), [0, 5, 0, 1, 0], [100, 30, 10, 4, 2]),
+])
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_round_sums_against_oracle(name, problem, first, count, mode):
+    """A whole round in the concurrent-stream (1), hipGraph (2) and persistent (3) modes against the
+    FP64 oracle on the same sample ranges: every level's six moment sums against math.fsum of the
+    oracle's per-sample values.  Bar, from the per-sample bar |dP| <= 1e-5 max(|P|, RMS(P)) (RMS of
+    the oracle's values over the range): each moment sum may move by the sum over samples of that
+    moment's first-order change, e.g. 2 |Y| (dPf + dPc) + (dPf + dPc)^2 for Y^2, plus 1e-13 of the
+    sum of magnitudes for the FP64 summation itself."""
+    import math
+    import oracle
+    L = len(count) - 1
+    print(f"[gpu] {name} round_mode={mode} counts {count} vs oracle", flush=True)
+    ctx = dk.Context(0)
+    got = dk.round_sums(problem, L, first, count, round_mode=mode, ctx=ctx)
+    ctx.close()
+    op = oracle.OracleProblem(problem)
+    for l in range(L + 1):
+        ref = oracle.run_range(op, l, first[l], count[l])          # [count][n_obs][2]
+        for j in range(len(problem.obs)):
+            pf, pc = ref[:, j, 0], ref[:, j, 1]
+            ef = 1e-5 * np.maximum(np.abs(pf), np.sqrt(np.mean(pf ** 2)))
+            ec = 1e-5 * np.maximum(np.abs(pc), np.sqrt(np.mean(pc ** 2)))
+            ey = ef + ec
+            y = pf - pc
+            bound = [ey, 2 * np.abs(y) * ey + ey ** 2, ef, 2 * np.abs(pf) * ef + ef ** 2, ec, 2 * np.abs(pc) * ec + ec ** 2]
+            m = got[l][j]
+            assert m.count == count[l]
+            for k, v in enumerate(_moment_values(pf, pc)):
+                ex = math.fsum(v)
+                tol = math.fsum(bound[k]) + 1e-13 * math.fsum(np.abs(v)) + 1e-300
+                assert abs(m.sums[k] - ex) <= tol, (name, mode, l, j, k, m.sums[k], ex, tol)

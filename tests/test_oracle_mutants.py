@@ -105,6 +105,28 @@ def pin_gauss_vs_fp64():
         np.all(np.abs(z1 - R * np.sin(th)) <= 1e-6 * np.maximum(1, R))
 
 
+def pin_bump_fields():
+    import test_oracle_fields as F
+    try:
+        for n in (64, 128):
+            for c in ((0.5, 0.5), (0.05, 0.05)):
+                F.test_bump_integral_and_second_moment(n, c)
+            F.test_bump_peak_on_the_centre_point(n)
+    except AssertionError:
+        return False
+    return True
+
+
+def pin_clipped_field():
+    import test_oracle_fields as F
+    try:
+        for n in (8, 64):
+            F.test_clipped_datum_mean_floor_and_max(n)
+    except AssertionError:
+        return False
+    return True
+
+
 MUTANTS = [
     # (name, old text, new text, pin that must fail)
     ("coarse increment without 2^{-d/2}", "dbc[k] *= 0.5;   /* 2^{-d/2}, d = 2 */", "dbc[k] *= 1.0;",
@@ -127,6 +149,12 @@ MUTANTS = [
      "double r = rho[s] > 0.0 ? rho[s] : 0.0;", "double r = fabs(rho[s]);", pin_dense_divergence),
     ("Box-Muller quadrant rotated the wrong way", "case 1: c = -sq; sn = cq; break;",
      "case 1: c = sq; sn = -cq; break;", pin_gauss_vs_fp64),
+    ("bump width sigma^2 in place of 2 sigma^2",
+     "exp(-(dx * dx + dy * dy) / (2.0 * f->bump_sigma * f->bump_sigma))",
+     "exp(-(dx * dx + dy * dy) / (f->bump_sigma * f->bump_sigma))", pin_bump_fields),
+    ("bump distance without the periodic wrap", "if (d > 0.5 * box) d = box - d;", "", pin_bump_fields),
+    ("floor added inside the positive part", "if (f->kind == FIELD_CLIPPED) v = (v > 0.0 ? v : 0.0) + f->floor_add;",
+     "if (f->kind == FIELD_CLIPPED) v = (v + f->floor_add > 0.0 ? v + f->floor_add : 0.0);", pin_clipped_field),
 ]
 
 
