@@ -251,6 +251,24 @@ int dk_mlmc_level_pair(dk_context* ctx, const dk_problem* problem, int32_t level
                        uint64_t first_sample, uint64_t n_samples, uint32_t stream_tag,
                        dk_moments* sums_out, double* per_sample_out, void* stream);
 
+/* Allocation-free variant of dk_mlmc_level_pair, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments and results without the context: runs on the current device and calls no hipMalloc,
+ * hipFree or other allocating routine.  Its workspace (level tables, the centring run, one chunk of
+ * per-sample values, chunk moments) is a fixed 32 MiB device array that each GPU the library runs
+ * on holds until the process ends; calls on one GPU share it, so calls that overlap on one GPU
+ * (other host threads, or other streams still running an earlier call) race.  Every table is
+ * rebuilt on each call (no cache; the noise-free centring run adds about one sample's time).
+ * Resident levels only (grids up to 128 x 128), explicit NN scheme; the default tile shape.
+ * Per-sample values equal dk_mlmc_level_pair's; moment sums may be grouped in other chunks
+ * (rounding-level differences).  Errors: as dk_mlmc_level_pair, plus DK_EINVAL when the level's
+ * tables and one chunk of per-sample values do not fit the 32 MiB (e.g. 128 x 128 with more than
+ * about 190 observables, never within DK_MAX_OBS) and DK_EUNSUPPORTED for streamed grids, the
+ * Fourier coupling or b0 > 0. */
+int dk_mlmc_level_pair_noalloc(const dk_problem* problem, int32_t level, uint64_t first_sample,
+                               uint64_t n_samples, uint32_t stream_tag, dk_moments* sums_out,
+                               double* per_sample_out, void* stream);
+
 /* Plain (single-level) Monte Carlo batch on level l (the baseline of Sec. 7): uncoupled
  * paths with the DK_TAG_MC stream; per_sample_out as above with P_coarse = 0. */
 int dk_mc_level(dk_context* ctx, const dk_problem* problem, int32_t level,

@@ -216,6 +216,26 @@ def level_pair(problem, level: int, first: int, n: int, tag: int = W.TAG_MLMC, p
     return (_moments(sums), out) if per_sample else _moments(sums)
 
 
+def level_pair_noalloc(problem, level: int, first: int, n: int, tag: int = W.TAG_MLMC, per_sample: bool = False,
+                       device: int = 0, stream=None):
+    """dk_mlmc_level_pair_noalloc: as level_pair, on the current device, with the library's fixed
+    device workspace (no context, no device allocation inside the call).  The optional per-sample
+    output tensor is allocated here, by the caller's side of the boundary."""
+    lib = L.load()
+    cp = _cp(problem)
+    nobs = len(cp.p.obs)
+    sums = (L.dk_moments * nobs)()
+    out = None
+    torch = _torch()
+    if per_sample:
+        out = torch.empty((n, nobs, 2), dtype=torch.float64, device=f"cuda:{device}")
+    if stream is None:
+        stream = torch.cuda.current_stream(device).cuda_stream
+    with torch.cuda.device(device):
+        _check(lib.dk_mlmc_level_pair_noalloc(cp.ref, level, first, n, tag, sums, _ptr(out), C.c_void_p(stream)))
+    return (_moments(sums), out) if per_sample else _moments(sums)
+
+
 def mc_level(problem, level: int, first: int, n: int, per_sample: bool = False, ctx: Context | None = None):
     ctx = ctx or default_context()
     cp = _cp(problem)

@@ -71,6 +71,8 @@ SIGNATURES = {
     "dk_mlmc_level_pair": (C.c_int, [C.c_void_p, C.POINTER(dk_problem), C.c_int32, C.c_uint64, C.c_uint64,
                                      C.c_uint32, C.POINTER(dk_moments), C.c_void_p, C.c_void_p]),
     "dk_moments_mean_var": (C.c_int, [C.POINTER(dk_moments), C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "dk_mlmc_level_pair_noalloc": (C.c_int, [C.POINTER(dk_problem), C.c_int32, C.c_uint64, C.c_uint64, C.c_uint32,
+                                             C.POINTER(dk_moments), C.c_void_p, C.c_void_p]),
     "dk_mc_level": (C.c_int, [C.c_void_p, C.POINTER(dk_problem), C.c_int32, C.c_uint64, C.c_uint64,
                               C.POINTER(dk_moments), C.c_void_p, C.c_void_p]),
     "dk_mlmc_round": (C.c_int, [C.c_void_p, C.POINTER(dk_problem), C.c_int32, C.POINTER(C.c_uint64),

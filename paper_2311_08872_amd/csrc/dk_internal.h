@@ -75,4 +75,13 @@ hipError_t launch_meanfield_stream(int n, double a, int steps, double* buf0, dou
 hipError_t launch_inner_products(const double* rho, int n, const double* phi, int n_obs, double h2,
                                  double* out, hipStream_t s);
 
+// Host side of the allocation-free level batch (dk_api.cpp): samples [first, first + count) of
+// resident level `level` (a pair for level >= 1) with every device buffer, the level tables and
+// the centring run included, carved from `arena` (device, arena_bytes, 256-byte aligned); returns a
+// dk status (DK_EINVAL when the tables and one chunk of per-sample values do not fit).
+int level_pair_arena(const dk_problem* p, int level, uint64_t first, uint64_t count, uint32_t tag, dk_moments* sums_out,
+                     double* per_sample_out, void* arena, size_t arena_bytes, hipStream_t s);
+// Sets the calling thread's dk_last_error() text and returns code.
+int set_error(int code, const char* msg);
+
 }  // namespace dk

@@ -13,6 +13,10 @@
 //              launch cap changed between them (buffers grow and shrink under a captured graph).
 //   stream     levels on the streaming path (forced at 64^2 and 128^2, native at 256^2), each
 //              temporal depth forced, then the automatic depth tuning, with several batches.
+//   arena      the allocation-free level batch (dk::level_pair_arena) on a 32 MiB arena against
+//              dk_mlmc_level_pair on a context: identical per-sample values, equal moment sums, on
+//              two calls in a row (the second smaller), with and without a per-sample output; an
+//              arena too small and a streamed grid are refused.
 //   errors     argument errors return negative codes.
 // At the end every stand-in device allocation, stream and event must have been released.
 #include <cmath>
@@ -22,7 +26,14 @@
 #include <string>
 #include <vector>
 
+#include <hip/hip_runtime.h>
+
 #include "../../../include/dk_mlmc.h"
+
+namespace dk {
+int level_pair_arena(const dk_problem* p, int level, uint64_t first, uint64_t count, uint32_t tag, dk_moments* sums_out,
+                     double* per_sample_out, void* arena, size_t arena_bytes, hipStream_t s);
+}
 
 extern std::vector<std::string> g_fake_errors;
 extern uint64_t g_fake_launches;
@@ -287,6 +298,58 @@ static void scenario_stream()
     stand_in_clean("stream");
 }
 
+static void scenario_arena()
+{
+    std::printf("[host] arena\n");
+    std::fflush(stdout);
+    Problem P;
+    make_hierarchy(P, 8, 5, 0.05);
+    const size_t arena_bytes = size_t(32) << 20;
+    void* arena = nullptr;
+    CHECK(hipMalloc(&arena, arena_bytes) == hipSuccess, "arena");
+    dk_context* ctx = nullptr;
+    CHECK(dk_context_create(&ctx, 0) == DK_OK, "context: %s", dk_last_error());
+    struct Call { int level; uint64_t first, count; };
+    const Call calls[] = {{4, 3, 700}, {4, 0, 41}, {0, 5, 300000}, {0, 1, 17}, {2, 0, 2000}, {1, 9, 0}};
+    for (int with_ps = 0; with_ps < 2; ++with_ps)
+        for (const Call& c : calls) {
+            const int nobs = P.p.n_obs;
+            std::vector<dk_moments> a(nobs), b(nobs);
+            double *psa = nullptr, *psb = nullptr;
+            const size_t psbytes = sizeof(double) * 2 * nobs * (c.count ? c.count : 1);
+            if (with_ps) {
+                CHECK(hipMalloc((void**)&psa, psbytes) == hipSuccess, "ps");
+                CHECK(hipMalloc((void**)&psb, psbytes) == hipSuccess, "ps");
+            }
+            const int ra = dk::level_pair_arena(&P.p, c.level, c.first, c.count, DK_TAG_MLMC, a.data(), psa, arena, arena_bytes, nullptr);
+            const int rb = dk_mlmc_level_pair(ctx, &P.p, c.level, c.first, c.count, DK_TAG_MLMC, b.data(), psb, nullptr);
+            CHECK(ra == DK_OK && rb == DK_OK, "level %d: %d / %d: %s", c.level, ra, rb, dk_last_error());
+            for (int j = 0; j < nobs; ++j) {
+                CHECK(a[j].count == b[j].count, "level %d obs %d: count", c.level, j);
+                for (int k = 0; k < DK_NMOM; ++k)
+                    CHECK(close_rel(a[j].sum[k] + a[j].comp[k], b[j].sum[k] + b[j].comp[k], 1e-13),
+                          "level %d obs %d moment %d: %.17g vs %.17g", c.level, j, k, a[j].sum[k] + a[j].comp[k],
+                          b[j].sum[k] + b[j].comp[k]);
+            }
+            if (with_ps) {
+                CHECK(std::memcmp(psa, psb, sizeof(double) * 2 * nobs * c.count) == 0, "level %d: per-sample values differ", c.level);
+                (void)hipFree(psa);
+                (void)hipFree(psb);
+            }
+            stand_in_clean("arena");
+        }
+    std::vector<dk_moments> m(P.p.n_obs);
+    CHECK(dk::level_pair_arena(&P.p, 4, 0, 10, 0, m.data(), nullptr, arena, size_t(256) << 10, nullptr) == DK_EINVAL,
+          "a 256 KiB arena was accepted for the 128^2 pair");
+    Problem Q;
+    make_hierarchy(Q, 64, 3, 32 * 0.1 / (64.0 * 64.0));
+    CHECK(dk::level_pair_arena(&Q.p, 2, 0, 10, 0, m.data(), nullptr, arena, arena_bytes, nullptr) == DK_EUNSUPPORTED,
+          "the streamed 256^2 level was accepted");
+    dk_context_destroy(ctx);
+    (void)hipFree(arena);
+    stand_in_clean("arena");
+}
+
 static void scenario_errors()
 {
     std::printf("[host] errors\n");
@@ -324,6 +387,7 @@ int main(int argc, char** argv)
     }
     if (only.empty() || only == "sequence") scenario_sequence();
     if (only.empty() || only == "stream") scenario_stream();
+    if (only.empty() || only == "arena") scenario_arena();
     if (only.empty() || only == "errors") scenario_errors();
     CHECK(fake_live_device_allocations() == base_alloc, "%d device allocations left after every context was destroyed",
           fake_live_device_allocations() - base_alloc);

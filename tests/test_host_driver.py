@@ -2,7 +2,8 @@
 UndefinedBehaviorSanitizer against CPU stand-ins of the HIP runtime and of the kernel launch layer
 (tests/native/host_fake), then driven through Algorithm 1 in every round mode (with the tile-shape
 tuner, small launch caps, a reused context whose buffers grow under a captured graph), the
-streaming path at every temporal depth and with its depth tuning, and argument errors.  The
+streaming path at every temporal depth and with its depth tuning, the allocation-free level batch on a
+fixed arena against the context path, and argument errors.  The
 stand-in kernels touch exactly the buffer extents of the real ones and produce per-sample values
 that the harness recomputes, so a wrong range, chunk, merge order or stale pointer fails here."""
 import os
@@ -38,7 +39,7 @@ def harness(tmp_path_factory):
     return exe
 
 
-@pytest.mark.parametrize("scenario", ["rounds", "sequence", "stream", "errors"])
+@pytest.mark.parametrize("scenario", ["rounds", "sequence", "stream", "arena", "errors"])
 def test_host_driver_under_sanitizers(harness, scenario):
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1",
                UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
