@@ -132,6 +132,41 @@ __global__ void __launch_bounds__(Geo<D>::THREADS, 4) stream_kernel(const Stream
             }
         }
     }
+    // Per-launch constants of the two deals, so that no step repeats the index arithmetic: for each
+    // cell slot its distance to the extended tile's edge, four to a register (the update region of
+    // step j is the cells at distance > j; 0 marks a slot past the tile); for each 2x2 block slot
+    // its first cell's LDS index, 1 + its distance in blocks to the edge (0 marks a slot past the
+    // tile) and whether it is in the last block column / row, and the generator index of its
+    // upper site pair with a flag for the wrap of its lower row.
+    uint32_t clay[(CPT + 3) / 4];
+#pragma unroll
+    for (int q = 0; q < (CPT + 3) / 4; ++q) clay[q] = 0u;
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+        const int i = t + k * THREADS;
+        if (i < NCELL) {
+            const int ex = i % EXT, ey = i / EXT;
+            const int lay = min(min(ex, EXT - 1 - ex), min(ey, EXT - 1 - ey));
+            clay[k / 4] |= (uint32_t)lay << (8 * (k % 4));
+        }
+    }
+    uint32_t binf[BPT], bidx[BPT];
+#pragma unroll
+    for (int k = 0; k < BPT; ++k) {
+        const int b = t + k * THREADS;
+        binf[k] = 0u;
+        bidx[k] = 0u;
+        if (b < NBLK) {
+            const int bx = b % NBS, by = b / NBS;
+            const int lay = min(min(bx, NBS - 1 - bx), min(by, NBS - 1 - by));
+            binf[k] = (uint32_t)(2 * by * EXT + 2 * bx) | ((uint32_t)(lay + 1) << 13) |
+                      ((uint32_t)(bx == NBS - 1) << 19) | ((uint32_t)(by == NBS - 1) << 20);
+            const int gy = wrapi(ty0 + 2 * by - HH, n);
+            const int gx = wrapi(tx0 + 2 * bx - HH, n);   // even
+            bidx[k] = ((uint32_t)(gx / 2) + ppr * (uint32_t)gy) | ((uint32_t)(gy == n - 1) << 31);
+        }
+    }
+    const uint32_t wrap_back = ppr * (uint32_t)(n - 1);   // lower row index of a block on the last row: gx / 2
     __syncthreads();
 
     const float a = A.a, kappa = A.kf;
@@ -140,25 +175,22 @@ __global__ void __launch_bounds__(Geo<D>::THREADS, 4) stream_kernel(const Stream
         // noise is needed on the flux region [j, EXT - j) and, for the fused coarse step, on the
         // blocks whose coarse cell is in the coarse tile plus its halo (ext [2, EXT - 2))
         const int lo = FUSED ? (j < 2 ? j : 2) : j;
-        const int hi = EXT - lo;
 #pragma unroll
         for (int k = 0; k < BPT; ++k) {
-            const int b = t + k * THREADS;
-            if (b >= NBLK) continue;
-            const int bx = b % NBS, by = b / NBS;
-            if (2 * bx + 2 <= lo || 2 * bx >= hi || 2 * by + 2 <= lo || 2 * by >= hi) continue;
+            const uint32_t lay1 = (binf[k] >> 13) & 0x3Fu;          // 1 + distance in blocks; 0: no block
+            if (lay1 <= (uint32_t)(lo >> 1)) continue;             // the block misses [lo, EXT - lo)
+            const int c0 = (int)(binf[k] & 0x1FFFu);
             float w0[4], w1[4];
+            const uint32_t idx0 = bidx[k] & 0x7FFFFFFFu;
+            const uint32_t idx1 = (bidx[k] >> 31) ? idx0 - wrap_back : idx0 + ppr;
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
-                const int gy = wrapi(ty0 + 2 * by + r - HH, n);
-                const int gx = wrapi(tx0 + 2 * bx - HH, n);   // even
-                uint32_t idx = (uint32_t)(gx / 2) + ppr * (uint32_t)gy;
                 float a0, a1, b0, b1;
-                site_pair_normals(key, idx, m, a0, a1, b0, b1);
+                site_pair_normals(key, r == 0 ? idx0 : idx1, m, a0, a1, b0, b1);
                 w0[2 * r] = a0; w1[2 * r] = a1; w0[2 * r + 1] = b0; w1[2 * r + 1] = b1;
             }
             if constexpr (FUSED) {
-                if (bx >= 1 && bx < NBS - 1 && by >= 1 && by < NBS - 1) {
+                if (lay1 >= 2u) {
                     Z[k][0] += (w0[0] + w0[1]) + (w0[2] + w0[3]);
                     Z[k][1] += (w1[0] + w1[1]) + (w1[2] + w1[3]);
                 }
@@ -169,16 +201,16 @@ __global__ void __launch_bounds__(Geo<D>::THREADS, 4) stream_kernel(const Stream
             // fluxes of all 4 cells: those outside this step's region get values no valid update reads
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int ex = 2 * bx + (q & 1), ey = 2 * by + (q >> 1);
-                const int c = ey * EXT + ex;
+                const int c = c0 + (q & 1) + (q >> 1) * EXT;
                 const float rv = sr[c];
                 if (FLUX == DK_FLUX_CENTRAL) {
                     const float sq = psq(rv);
                     sf0[c] = sq * w0[q];
                     sf1[c] = sq * w1[q];
                 } else {
-                    const float rx = sr[ex + 1 < EXT ? c + 1 : c];
-                    const float ry = sr[ey + 1 < EXT ? c + EXT : c];
+                    const bool last_x = (q & 1) && ((binf[k] >> 19) & 1u), last_y = (q >> 1) && ((binf[k] >> 20) & 1u);
+                    const float rx = sr[last_x ? c : c + 1];
+                    const float ry = sr[last_y ? c : c + EXT];
                     sf0[c] = psq(0.5f * (rv + rx)) * w0[q];
                     sf1[c] = psq(0.5f * (rv + ry)) * w1[q];
                 }
@@ -191,7 +223,7 @@ __global__ void __launch_bounds__(Geo<D>::THREADS, 4) stream_kernel(const Stream
                 for (int k = 0; k < BPT; ++k) {
                     const int b = t + k * THREADS;
                     const int bx = b % NBS, by = b / NBS;
-                    if (b < NBLK && interior(bx, by)) *zslot(bx, by, D == 8 ? (j >> 2) : 0) = make_float2(Z[k][0], Z[k][1]);
+                    if (((binf[k] >> 13) & 0x3Fu) > (uint32_t)HB) *zslot(bx, by, D == 8 ? (j >> 2) : 0) = make_float2(Z[k][0], Z[k][1]);
                     Z[k][0] = 0.f;
                     Z[k][1] = 0.f;
                 }
@@ -204,9 +236,7 @@ __global__ void __launch_bounds__(Geo<D>::THREADS, 4) stream_kernel(const Stream
         for (int k = 0; k < CPT; ++k) {
             const int i = t + k * THREADS;
             nv[k] = 0.f;
-            if (i >= NCELL) continue;
-            const int ex = i % EXT, ey = i / EXT;
-            if (ex <= j || ex >= EXT - j - 1 || ey <= j || ey >= EXT - j - 1) continue;
+            if (((clay[k / 4] >> (8 * (k % 4))) & 0xFFu) <= (uint32_t)j) continue;
             const int c = i;
             const float rv = sr[c];
             const float lap = fmaf(-4.0f, rv, (sr[c - 1] + sr[c + 1]) + (sr[c - EXT] + sr[c + EXT]));
@@ -223,9 +253,7 @@ __global__ void __launch_bounds__(Geo<D>::THREADS, 4) stream_kernel(const Stream
 #pragma unroll
         for (int k = 0; k < CPT; ++k) {
             const int i = t + k * THREADS;
-            if (i >= NCELL) continue;
-            const int ex = i % EXT, ey = i / EXT;
-            if (ex <= j || ex >= EXT - j - 1 || ey <= j || ey >= EXT - j - 1) continue;
+            if (((clay[k / 4] >> (8 * (k % 4))) & 0xFFu) <= (uint32_t)j) continue;
             sr[i] = nv[k];
         }
         __syncthreads();
