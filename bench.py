@@ -557,14 +557,16 @@ def bench_config3(args):
        the low-density behaviour (V_l stops decreasing once N h^2 rho is small).
     2. Algorithm 1 with persistent rounds.  The primary observable is uncentred and unscaled
        (about 1.5e-4), so the accuracy is relative to its magnitude, estimated by a 1000-sample
-       level-0 pilot from another noise stream: 1e-3 at N = 1e5 (reaches 256^2) and 3e-2 at
-       N = 1e3 (where the growing V_l make tighter targets cost hours); --N with --eps overrides.
+       level-0 pilot from another noise stream: 1e-3 at N = 1e5 (reaches 256^2) and 1.5e-2 at
+       N = 1e3 (there the level means grow from 32^2 on, so the bias test does not pass and the run
+       ends on 256^2 with the variance target met, in about 4 minutes; a looser 3e-2 passes the
+       bias test on 16^2 by chance); --N with --eps overrides.
     Reports wall times, the share of wall time outside kernels, the tuner's choices and the
     per-level statistics."""
     import torch
     import dk_workloads as W
     import paper_2311_08872_amd as dk
-    runs = [(args.N, args.eps)] if args.N else [(1e5, 1e-3), (1e3, 3e-2)]
+    runs = [(args.N, args.eps)] if args.N else [(1e5, 1e-3), (1e3, 1.5e-2)]
     for N, rel in runs:
         p = W.config3(N=N)
         L = p.levels - 1

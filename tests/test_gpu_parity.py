@@ -146,6 +146,25 @@ def test_config3_low_density_per_sample_parity(level, count):
     assert err <= TOL
 
 
+def test_config3_low_density_fp64_state_agrees_where_conditioning_allows():
+    """The same low-density problem (config 3, N = 1e3, 32^2 pairs, 29 observables) with the FP64
+    state: the kernels' arithmetic is the oracle's up to rounding order, so most values agree to
+    rounding (median scaled difference <= 1e-12), and the few samples whose paths pass close to 0
+    move by at most what the problem's own conditioning allows (the oracle's values move by up to
+    1.6e-6 of their RMS when its input moves by 1e-15; bar 1e-3)."""
+    p = W.config3(N=1e3).with_(precision=W.PREC_F64)
+    level, count = 2, 200
+    banner(f"config3 N=1e3 FP64 level={level} count={count}")
+    _, ps = dk.level_pair(p, level, 3, count, per_sample=True)
+    torch.cuda.synchronize()
+    gpu = ps.cpu().numpy().reshape(count, -1)
+    ref = oracle.run_range(oracle.OracleProblem(p), level, 3, count).reshape(count, -1)
+    e = scaled_err_each(gpu, ref)
+    banner(f"FP64 scaled differences: median {np.median(e):.3g}, max {e.max():.3g}")
+    assert np.median(e) <= 1e-12
+    assert e.max() <= 1e-3
+
+
 @pytest.mark.parametrize("level,count", [(2, 200), (3, 64), (4, 16)])
 def test_config3_low_density_estimator_parity(level, count):
     """Config 3 at N = 1e3 on the resident levels where its sample paths are ill conditioned
