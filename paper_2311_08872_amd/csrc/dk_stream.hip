@@ -2,7 +2,7 @@
 // of 64 works), with the state in HBM and temporal blocking of depth D in {1, 2, 4, 8}.
 //
 // One launch advances a batch of samples by up to D fine steps.  Each block owns a 64 x 64 fine
-// tile of one sample and loads it with a halo of H = max(D, 2) cells into LDS (H is even so that
+// tile of one sample and loads it with a halo of H = max(D, 2) cells (H is even so that
 // the 2 x 2 blocks below line up with the coarse cells and with the horizontal site pairs that
 // share a generator call).  The noise of the halo is regenerated from the counter-based
 // generator (it is a pure function of site and step), so no noise is exchanged; the valid
@@ -22,9 +22,8 @@
 // kernel, so every depth produces bit-identical fields.
 //
 // Lane work: a block of 512 threads (640 at D = 8) owns the (32 + H)^2 2x2 blocks of the extended
-// tile, up to three per thread (thread t owns blocks t, t + 512, t + 1024); each 2x2 block is two
-// generator calls per step (one per horizontal site pair) and holds its coarse cell's noise sum in
-// registers.
+// tile, up to three per thread, and keeps their cells in registers for the whole launch; LDS only
+// passes the cells and fluxes that neighbouring blocks read (two barriers per fine step).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -35,42 +34,72 @@ namespace dk {
 
 namespace {
 constexpr int TT = 64;               // fine tile interior
-constexpr int CT = TT / 2;           // coarse tile interior (32)
-constexpr int CEXT = CT + 2;         // coarse tile with a 1-cell halo (34), fused coarse step
 
 template <int D>
 struct Geo {
     // 3 blocks per thread at every depth (448 threads would idle fewer slots at D <= 4 but hold 14
-    // wavefronts per compute unit instead of 16, and ran 19 % slower)
+    // wavefronts per compute unit instead of 16)
     static constexpr int THREADS = D == 8 ? 640 : 512;
     static constexpr int HH = D < 2 ? 2 : D;                  // halo width
     static constexpr int EXT = TT + 2 * HH;                   // extended tile side
     static constexpr int NBS = EXT / 2;                       // 2x2 blocks per side
     static constexpr int NBLK = NBS * NBS;
     static constexpr int BPT = (NBLK + THREADS - 1) / THREADS;
-    static constexpr int NCELL = EXT * EXT;
-    static constexpr int CPT = (NCELL + THREADS - 1) / THREADS;   // cells per thread, row-major deal
+    // LDS planes hold the extended tile with one pad row above and below and two pad columns on
+    // each side: the neighbour reads of the outermost blocks stay inside the plane, and every
+    // block's first cell is even (8-byte aligned pairs)
+    static constexpr int P = EXT + 4;                         // row pitch
+    static constexpr int PLANE = P * (EXT + 2);
+    // register budget: two blocks per compute unit at D <= 4; at D = 8 the LDS planes admit one
+    static constexpr int WAVES_PER_SIMD = D == 8 ? 3 : 4;
 };
 
 __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 // sqrt([x]^+) with [x]^+ as a signed integer maximum of the bits (negative values and -0 become
 // +0), the same as the resident kernel's, one instruction shorter than fmaxf in IEEE mode
 __device__ __forceinline__ float psq(float x) { return __builtin_amdgcn_sqrtf(__int_as_float(max(__float_as_int(x), 0))); }
+__device__ __forceinline__ float2 lds2(const float* p) { return *(const float2*)p; }
+__device__ __forceinline__ void lds2(float* p, float x, float y) { *(float2*)p = make_float2(x, y); }
+
+// One cell's explicit EM update with the Kahan-compensated increment: the operation sequence of
+// the resident kernel (lap = fma(-4, rho, (left + right) + (up + down)), d = fma(kappa, div,
+// a lap), compensation fed back), so both give bit-identical fields.
+__device__ __forceinline__ void em_cell(float& r, float& cm, float l, float rt, float u, float dn, float div, float a,
+                                        float kappa)
+{
+#pragma clang fp contract(off)
+    const float lap = fmaf(-4.0f, r, (l + rt) + (u + dn));
+    const float d = fmaf(kappa, div, a * lap);
+    const float y = d - cm;
+    const float tv = r + y;
+    cm = (tv - r) - y;
+    r = tv;
+}
 }  // namespace
 
+// Lane work: the threads own the 2x2 blocks of the extended tile (thread t holds blocks t,
+// t + THREADS, t + 2 THREADS in row-major block order) and keep their cells' density and
+// compensation in registers for all D steps.  A block is one generator call per row (the row's
+// horizontal site pair) and its coarse cell's noise sum.  LDS only carries what the neighbouring
+// blocks read: each step a block publishes its density and fluxes, and after one barrier reads
+// the adjacent cells of the blocks around it.  A block takes part in step j while it meets that
+// step's region: blocks at block distance L from the extended tile's edge hold cells at distances
+// 2L and 2L + 1, the fluxes are needed at distance >= j and the updates at distance >= j + 1.
+// Cells a block computes outside those regions hold values no valid cell reads.
 template <int FLUX, bool PAIR, int D>
-__global__ void __launch_bounds__(Geo<D>::THREADS, 4) stream_kernel(const StreamArgs A)
+__global__ void __launch_bounds__(Geo<D>::THREADS, Geo<D>::WAVES_PER_SIMD) stream_kernel(const StreamArgs A)
 {
 #pragma clang fp contract(off)
     constexpr int THREADS = Geo<D>::THREADS;
     constexpr int HH = Geo<D>::HH, EXT = Geo<D>::EXT, NBS = Geo<D>::NBS, NBLK = Geo<D>::NBLK, BPT = Geo<D>::BPT;
-    constexpr int NCELL = Geo<D>::NCELL, CPT = Geo<D>::CPT;
+    constexpr int P = Geo<D>::P, PLANE = Geo<D>::PLANE;
     constexpr bool FUSED = PAIR && D == 4;     // coarse step taken by this kernel
     constexpr bool SPLIT = PAIR && D != 4;     // noise sums kept in HBM, coarse step by its own kernel
     constexpr int HB = HH / 2;                 // first block of the tile interior
-    __shared__ float sr[EXT * EXT];
-    __shared__ float sf0[EXT * EXT];
-    __shared__ float sf1[EXT * EXT];
+    static_assert(PLANE < (1 << 13) && NBS / 2 + 1 < (1 << 6), "block descriptor fields");
+    __shared__ __align__(16) float sr[PLANE];
+    __shared__ __align__(16) float sf0[PLANE];
+    __shared__ __align__(16) float sf1[PLANE];
     const int n = A.n;
     const int tiles_x = n / TT;
     // Workgroups are handed to the 8 compute dies in turn by their index; this numbering gives each
@@ -78,8 +107,8 @@ __global__ void __launch_bounds__(Geo<D>::THREADS, 4) stream_kernel(const Stream
     // whose columns a tile's halo reads sit in the same die's L2 (numbering by tile index would put
     // them on other dies and fetch every horizontal halo line from HBM a second time).
     const unsigned total = gridDim.x, per = total / 8u, rem = total % 8u;
-    const unsigned die = blockIdx.x % 8u, k = blockIdx.x / 8u;
-    const unsigned lin = (die < rem ? die * (per + 1u) : rem * (per + 1u) + (die - rem) * per) + k;
+    const unsigned die = blockIdx.x % 8u, kd = blockIdx.x / 8u;
+    const unsigned lin = (die < rem ? die * (per + 1u) : rem * (per + 1u) + (die - rem) * per) + kd;
     const int tile = (int)(lin % (unsigned)(tiles_x * tiles_x));
     const int sidx = (int)(lin / (unsigned)(tiles_x * tiles_x));
     const int tx0 = (tile % tiles_x) * TT, ty0 = (tile / tiles_x) * TT;
@@ -87,10 +116,12 @@ __global__ void __launch_bounds__(Geo<D>::THREADS, 4) stream_kernel(const Stream
     const int nc = n / 2;
     const uint64_t sample = A.first + sidx;
     const size_t nn = (size_t)n * n;
-    const float* rin = A.rho_in + sidx * nn;
-    const float* cin = A.cmp_in + sidx * nn;
-    float* rout = A.rho_out + sidx * nn;
-    float* cout = A.cmp_out + sidx * nn;
+    // per-sample bases; cells are addressed by 32-bit byte offsets from them (n <= 32768)
+    const char* rin = (const char*)(A.rho_in + sidx * nn);
+    const char* cin = (const char*)(A.cmp_in + sidx * nn);
+    char* rout = (char*)(A.rho_out + sidx * nn);
+    char* cout = (char*)(A.cmp_out + sidx * nn);
+    auto at = [n](int y, int x) { return 4u * ((uint32_t)y * (uint32_t)n + (uint32_t)x); };
     const int t = threadIdx.x;
     const NoiseKey key = make_key(A.seed, A.tag, A.level_id, sample);
     const uint32_t ppr = (uint32_t)(n / 2);
@@ -98,121 +129,172 @@ __global__ void __launch_bounds__(Geo<D>::THREADS, 4) stream_kernel(const Stream
     auto zslot = [&](int bx, int by, int group) -> float2* {
         return (float2*)A.z + group * A.zgroup + ((size_t)sidx * nc + (cy0 + by - HB)) * nc + (cx0 + bx - HB);
     };
-    auto interior = [&](int bx, int by) { return bx >= HB && bx < HB + CT && by >= HB && by < HB + CT; };
 
-    // Two deals of the extended tile to the threads: 2x2 blocks (b = t + k THREADS) for the noise,
-    // whose generator calls cover horizontal site pairs and whose restriction sums 2x2 cells, and
-    // single cells in row-major order (i = t + k THREADS) for the update, so that the lanes of a
-    // wavefront read and write consecutive LDS words (no bank conflicts) and the halo's shrinking
-    // update region is shared out cell by cell.
-    float cmp[CPT], Z[BPT][2];
-    // load the extended tile (and, continuing a group, the running noise sums)
-#pragma unroll
-    for (int k = 0; k < CPT; ++k) {
-        const int i = t + k * THREADS;
-        cmp[k] = 0.f;
-        if (i < NCELL) {
-            const int ex = i % EXT, ey = i / EXT;
-            const int gx = wrapi(tx0 + ex - HH, n), gy = wrapi(ty0 + ey - HH, n);
-            sr[i] = rin[(size_t)gy * n + gx];
-            cmp[k] = cin[(size_t)gy * n + gx];
-        }
+    // zero the pad cells (read only by the outermost blocks, whose results are never used)
+    for (int i = t; i < 2 * P + 4 * EXT; i += THREADS) {
+        const int e = i - 2 * P;   // side pads: 4 per row, 2 on the left and 2 on the right
+        const int c = i < 2 * P ? (i < P ? i : PLANE - 2 * P + i) : (1 + e / 4) * P + ((e & 3) < 2 ? (e & 3) : P - 4 + (e & 3));
+        sr[c] = 0.f;
+        sf0[c] = 0.f;
+        sf1[c] = 0.f;
     }
-#pragma unroll
-    for (int k = 0; k < BPT; ++k) {
-        const int b = t + k * THREADS;
-        Z[k][0] = 0.f;
-        Z[k][1] = 0.f;
-        if constexpr (SPLIT) {
-            const int bx = b % NBS, by = b / NBS;
-            if (b < NBLK && A.z_load && interior(bx, by)) {
-                const float2 zz = *zslot(bx, by, 0);
-                Z[k][0] = zz.x;
-                Z[k][1] = zz.y;
-            }
-        }
-    }
-    // Per-launch constants of the two deals, so that no step repeats the index arithmetic: for each
-    // cell slot its distance to the extended tile's edge, four to a register (the update region of
-    // step j is the cells at distance > j; 0 marks a slot past the tile); for each 2x2 block slot
-    // its first cell's LDS index, 1 + its distance in blocks to the edge (0 marks a slot past the
-    // tile) and whether it is in the last block column / row, and the generator index of its
-    // upper site pair with a flag for the wrap of its lower row.
-    uint32_t clay[(CPT + 3) / 4];
-#pragma unroll
-    for (int q = 0; q < (CPT + 3) / 4; ++q) clay[q] = 0u;
-#pragma unroll
-    for (int k = 0; k < CPT; ++k) {
-        const int i = t + k * THREADS;
-        if (i < NCELL) {
-            const int ex = i % EXT, ey = i / EXT;
-            const int lay = min(min(ex, EXT - 1 - ex), min(ey, EXT - 1 - ey));
-            clay[k / 4] |= (uint32_t)lay << (8 * (k % 4));
-        }
-    }
+
+    // Per block: the two rows of its density and compensation, its noise sums, and two descriptor
+    // words: its first cell's LDS index | (1 + block distance to the edge) << 13 (0: no block), and
+    // the generator index of its upper site pair | a flag for the wrap of its lower row.
+    float r[BPT][4], cm[BPT][4], Z[BPT][2];
     uint32_t binf[BPT], bidx[BPT];
 #pragma unroll
     for (int k = 0; k < BPT; ++k) {
         const int b = t + k * THREADS;
         binf[k] = 0u;
         bidx[k] = 0u;
+        Z[k][0] = 0.f;
+        Z[k][1] = 0.f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) { r[k][q] = 0.f; cm[k][q] = 0.f; }
         if (b < NBLK) {
             const int bx = b % NBS, by = b / NBS;
             const int lay = min(min(bx, NBS - 1 - bx), min(by, NBS - 1 - by));
-            binf[k] = (uint32_t)(2 * by * EXT + 2 * bx) | ((uint32_t)(lay + 1) << 13) |
-                      ((uint32_t)(bx == NBS - 1) << 19) | ((uint32_t)(by == NBS - 1) << 20);
+            binf[k] = (uint32_t)((2 * by + 1) * P + 2 * bx + 2) | ((uint32_t)(lay + 1) << 13);
             const int gy = wrapi(ty0 + 2 * by - HH, n);
+            const int gy1 = gy + 1 == n ? 0 : gy + 1;
             const int gx = wrapi(tx0 + 2 * bx - HH, n);   // even
             bidx[k] = ((uint32_t)(gx / 2) + ppr * (uint32_t)gy) | ((uint32_t)(gy == n - 1) << 31);
+            const float2 r0 = *(const float2*)(rin + at(gy, gx));
+            const float2 r1 = *(const float2*)(rin + at(gy1, gx));
+            const float2 c0 = *(const float2*)(cin + at(gy, gx));
+            const float2 c1 = *(const float2*)(cin + at(gy1, gx));
+            r[k][0] = r0.x; r[k][1] = r0.y; r[k][2] = r1.x; r[k][3] = r1.y;
+            cm[k][0] = c0.x; cm[k][1] = c0.y; cm[k][2] = c1.x; cm[k][3] = c1.y;
+            if constexpr (SPLIT) {
+                if (A.z_load && lay >= HB) {
+                    const float2 zz = *zslot(bx, by, 0);
+                    Z[k][0] = zz.x;
+                    Z[k][1] = zz.y;
+                }
+            }
         }
     }
     const uint32_t wrap_back = ppr * (uint32_t)(n - 1);   // lower row index of a block on the last row: gx / 2
-    __syncthreads();
+
+    // the unit normals of block k at step m, added to its coarse cell's sums as (upper row sum +
+    // lower row sum)
+    auto draw = [&](int k, uint32_t m, float (&w0)[4], float (&w1)[4]) {
+        const uint32_t idx0 = bidx[k] & 0x7FFFFFFFu;
+        const uint32_t idx1 = (bidx[k] >> 31) ? idx0 - wrap_back : idx0 + ppr;
+        site_pair_normals(key, idx0, m, w0[0], w1[0], w0[1], w1[1]);
+        site_pair_normals(key, idx1, m, w0[2], w1[2], w0[3], w1[3]);
+        if constexpr (PAIR) {
+            Z[k][0] += (w0[0] + w0[1]) + (w0[2] + w0[3]);
+            Z[k][1] += (w1[0] + w1[1]) + (w1[2] + w1[3]);
+        }
+    };
 
     const float a = A.a, kappa = A.kf;
     for (int j = 0; j < A.ksteps; ++j) {
         const uint32_t m = (uint32_t)(A.m0 + j);
-        // noise is needed on the flux region [j, EXT - j) and, for the fused coarse step, on the
-        // blocks whose coarse cell is in the coarse tile plus its halo (ext [2, EXT - 2))
-        const int lo = FUSED ? (j < 2 ? j : 2) : j;
+        const uint32_t lo_flux = (uint32_t)(j >> 1) + 1u;         // 1 + least block distance of the flux region
+        const uint32_t lo_upd = (uint32_t)((j + 1) >> 1) + 1u;    // ... of the update region
+        float f0k[BPT][4], f1k[BPT][4];
+        if constexpr (FLUX == DK_FLUX_CENTRAL) {
+            // publish density and node fluxes sqrt(rho^+) w
 #pragma unroll
-        for (int k = 0; k < BPT; ++k) {
-            const uint32_t lay1 = (binf[k] >> 13) & 0x3Fu;          // 1 + distance in blocks; 0: no block
-            if (lay1 <= (uint32_t)(lo >> 1)) continue;             // the block misses [lo, EXT - lo)
-            const int c0 = (int)(binf[k] & 0x1FFFu);
-            float w0[4], w1[4];
-            const uint32_t idx0 = bidx[k] & 0x7FFFFFFFu;
-            const uint32_t idx1 = (bidx[k] >> 31) ? idx0 - wrap_back : idx0 + ppr;
+            for (int k = 0; k < BPT; ++k) {
+                if ((binf[k] >> 13) < lo_flux) continue;
+                const int c0 = (int)(binf[k] & 0x1FFFu);
+                float w0[4], w1[4];
+                draw(k, m, w0, w1);
+                float (&f0)[4] = f0k[k];
+                float (&f1)[4] = f1k[k];
 #pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                float a0, a1, b0, b1;
-                site_pair_normals(key, r == 0 ? idx0 : idx1, m, a0, a1, b0, b1);
-                w0[2 * r] = a0; w1[2 * r] = a1; w0[2 * r + 1] = b0; w1[2 * r + 1] = b1;
-            }
-            if constexpr (FUSED) {
-                if (lay1 >= 2u) {
-                    Z[k][0] += (w0[0] + w0[1]) + (w0[2] + w0[3]);
-                    Z[k][1] += (w1[0] + w1[1]) + (w1[2] + w1[3]);
+                for (int q = 0; q < 4; ++q) {
+                    const float sq = psq(r[k][q]);
+                    f0[q] = sq * w0[q];
+                    f1[q] = sq * w1[q];
                 }
-            } else if constexpr (SPLIT) {
-                Z[k][0] += (w0[0] + w0[1]) + (w0[2] + w0[3]);
-                Z[k][1] += (w1[0] + w1[1]) + (w1[2] + w1[3]);
+                lds2(sr + c0, r[k][0], r[k][1]);
+                lds2(sr + c0 + P, r[k][2], r[k][3]);
+                lds2(sf0 + c0, f0[0], f0[1]);
+                lds2(sf0 + c0 + P, f0[2], f0[3]);
+                lds2(sf1 + c0, f1[0], f1[1]);
+                lds2(sf1 + c0 + P, f1[2], f1[3]);
             }
-            // fluxes of all 4 cells: those outside this step's region get values no valid update reads
+        } else {
+            // publish density; the edge fluxes need the right and lower neighbours' densities
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int c = c0 + (q & 1) + (q >> 1) * EXT;
-                const float rv = sr[c];
-                if (FLUX == DK_FLUX_CENTRAL) {
-                    const float sq = psq(rv);
-                    sf0[c] = sq * w0[q];
-                    sf1[c] = sq * w1[q];
-                } else {
-                    const bool last_x = (q & 1) && ((binf[k] >> 19) & 1u), last_y = (q >> 1) && ((binf[k] >> 20) & 1u);
-                    const float rx = sr[last_x ? c : c + 1];
-                    const float ry = sr[last_y ? c : c + EXT];
-                    sf0[c] = psq(0.5f * (rv + rx)) * w0[q];
-                    sf1[c] = psq(0.5f * (rv + ry)) * w1[q];
+            for (int k = 0; k < BPT; ++k) {
+                if ((binf[k] >> 13) < lo_flux) continue;
+                const int c0 = (int)(binf[k] & 0x1FFFu);
+                lds2(sr + c0, r[k][0], r[k][1]);
+                lds2(sr + c0 + P, r[k][2], r[k][3]);
+            }
+        }
+        __syncthreads();
+        if constexpr (FLUX == DK_FLUX_CENTRAL) {
+#pragma unroll
+            for (int k = 0; k < BPT; ++k) {
+                if ((binf[k] >> 13) < lo_upd) continue;
+                const int c0 = (int)(binf[k] & 0x1FFFu);
+                const float2 up = lds2(sr + c0 - P), dn = lds2(sr + c0 + 2 * P);
+                const float l0 = lds2(sr + c0 - 2).y, l1 = lds2(sr + c0 + P - 2).y;
+                const float r0 = lds2(sr + c0 + 2).x, r1 = lds2(sr + c0 + P + 2).x;
+                const float2 f0a = make_float2(f0k[k][0], f0k[k][1]), f0b = make_float2(f0k[k][2], f0k[k][3]);
+                const float fl0 = lds2(sf0 + c0 - 2).y, fl1 = lds2(sf0 + c0 + P - 2).y;
+                const float fr0 = lds2(sf0 + c0 + 2).x, fr1 = lds2(sf0 + c0 + P + 2).x;
+                const float2 f1u = lds2(sf1 + c0 - P), f1a = make_float2(f1k[k][0], f1k[k][1]),
+                             f1b = make_float2(f1k[k][2], f1k[k][3]), f1d = lds2(sf1 + c0 + 2 * P);
+                const float o0 = r[k][0], o1 = r[k][1], o2 = r[k][2], o3 = r[k][3];
+                // div = (right x-flux - left x-flux) + (lower y-flux - upper y-flux)
+                em_cell(r[k][0], cm[k][0], l0, o1, up.x, o2, (f0a.y - fl0) + (f1b.x - f1u.x), a, kappa);
+                em_cell(r[k][1], cm[k][1], o0, r0, up.y, o3, (fr0 - f0a.x) + (f1b.y - f1u.y), a, kappa);
+                em_cell(r[k][2], cm[k][2], l1, o3, o0, dn.x, (f0b.y - fl1) + (f1d.x - f1a.x), a, kappa);
+                em_cell(r[k][3], cm[k][3], o2, r1, o1, dn.y, (fr1 - f0b.x) + (f1d.y - f1a.y), a, kappa);
+            }
+        } else {
+            // edge fluxes psq((rho + right) / 2) w0 and psq((rho + lower) / 2) w1; the Laplacian
+            // is formed here, where the neighbours' densities are read
+            float lap4[BPT][4];
+#pragma unroll
+            for (int k = 0; k < BPT; ++k) {
+                if ((binf[k] >> 13) < lo_flux) continue;
+                const int c0 = (int)(binf[k] & 0x1FFFu);
+                float w0[4], w1[4];
+                draw(k, m, w0, w1);
+                const float2 up = lds2(sr + c0 - P), dn = lds2(sr + c0 + 2 * P);
+                const float l0 = lds2(sr + c0 - 2).y, l1 = lds2(sr + c0 + P - 2).y;
+                const float r0 = lds2(sr + c0 + 2).x, r1 = lds2(sr + c0 + P + 2).x;
+                const float o0 = r[k][0], o1 = r[k][1], o2 = r[k][2], o3 = r[k][3];
+                const float f0[4] = {psq(0.5f * (o0 + o1)) * w0[0], psq(0.5f * (o1 + r0)) * w0[1],
+                                     psq(0.5f * (o2 + o3)) * w0[2], psq(0.5f * (o3 + r1)) * w0[3]};
+                const float f1[4] = {psq(0.5f * (o0 + o2)) * w1[0], psq(0.5f * (o1 + o3)) * w1[1],
+                                     psq(0.5f * (o2 + dn.x)) * w1[2], psq(0.5f * (o3 + dn.y)) * w1[3]};
+                lds2(sf0 + c0, f0[0], f0[1]);
+                lds2(sf0 + c0 + P, f0[2], f0[3]);
+                lds2(sf1 + c0, f1[0], f1[1]);
+                lds2(sf1 + c0 + P, f1[2], f1[3]);
+                lap4[k][0] = fmaf(-4.0f, o0, (l0 + o1) + (up.x + o2));
+                lap4[k][1] = fmaf(-4.0f, o1, (o0 + r0) + (up.y + o3));
+                lap4[k][2] = fmaf(-4.0f, o2, (l1 + o3) + (o0 + dn.x));
+                lap4[k][3] = fmaf(-4.0f, o3, (o2 + r1) + (o1 + dn.y));
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < BPT; ++k) {
+                if ((binf[k] >> 13) < lo_upd) continue;
+                const int c0 = (int)(binf[k] & 0x1FFFu);
+                const float2 f0a = lds2(sf0 + c0), f0b = lds2(sf0 + c0 + P);
+                const float fl0 = lds2(sf0 + c0 - 2).y, fl1 = lds2(sf0 + c0 + P - 2).y;
+                const float2 f1u = lds2(sf1 + c0 - P), f1a = lds2(sf1 + c0), f1b = lds2(sf1 + c0 + P);
+                const float div[4] = {(f0a.x - fl0) + (f1a.x - f1u.x), (f0a.y - f0a.x) + (f1a.y - f1u.y),
+                                      (f0b.x - fl1) + (f1b.x - f1a.x), (f0b.y - f0b.x) + (f1b.y - f1a.y)};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float d = fmaf(kappa, div[q], a * lap4[k][q]);
+                    const float y = d - cm[k][q];
+                    const float tv = r[k][q] + y;
+                    cm[k][q] = (tv - r[k][q]) - y;
+                    r[k][q] = tv;
                 }
             }
         }
@@ -222,108 +304,86 @@ __global__ void __launch_bounds__(Geo<D>::THREADS, 4) stream_kernel(const Stream
 #pragma unroll
                 for (int k = 0; k < BPT; ++k) {
                     const int b = t + k * THREADS;
-                    const int bx = b % NBS, by = b / NBS;
-                    if (((binf[k] >> 13) & 0x3Fu) > (uint32_t)HB) *zslot(bx, by, D == 8 ? (j >> 2) : 0) = make_float2(Z[k][0], Z[k][1]);
+                    if ((binf[k] >> 13) > (uint32_t)HB)
+                        *zslot(b % NBS, b / NBS, D == 8 ? (j >> 2) : 0) = make_float2(Z[k][0], Z[k][1]);
                     Z[k][0] = 0.f;
                     Z[k][1] = 0.f;
                 }
             }
         }
-        __syncthreads();
-        // update region [j + 1, EXT - j - 1), one cell per deal slot
-        float nv[CPT];
-#pragma unroll
-        for (int k = 0; k < CPT; ++k) {
-            const int i = t + k * THREADS;
-            nv[k] = 0.f;
-            if (((clay[k / 4] >> (8 * (k % 4))) & 0xFFu) <= (uint32_t)j) continue;
-            const int c = i;
-            const float rv = sr[c];
-            const float lap = fmaf(-4.0f, rv, (sr[c - 1] + sr[c + 1]) + (sr[c - EXT] + sr[c + EXT]));
-            float div;
-            if (FLUX == DK_FLUX_CENTRAL) div = (sf0[c + 1] - sf0[c - 1]) + (sf1[c + EXT] - sf1[c - EXT]);
-            else div = (sf0[c] - sf0[c - 1]) + (sf1[c] - sf1[c - EXT]);
-            const float d = fmaf(kappa, div, a * lap);
-            const float y = d - cmp[k];
-            const float tv = rv + y;
-            cmp[k] = (tv - rv) - y;
-            nv[k] = tv;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < CPT; ++k) {
-            const int i = t + k * THREADS;
-            if (((clay[k / 4] >> (8 * (k % 4))) & 0xFFu) <= (uint32_t)j) continue;
-            sr[i] = nv[k];
-        }
-        __syncthreads();
+        // Central fluxes: the next step's writes must wait for this step's reads.  Edge fluxes
+        // need no barrier here: the next density writes follow the flux barrier above, after the
+        // last density read, and the next flux writes follow the next step's first barrier.
+        if constexpr (FLUX == DK_FLUX_CENTRAL) __syncthreads();
     }
-    // write back the interior
+    // write back the interior blocks
 #pragma unroll
-    for (int k = 0; k < CPT; ++k) {
-        const int i = t + k * THREADS;
-        if (i >= NCELL) continue;
-        const int ex = i % EXT, ey = i / EXT;
-        if (ex < HH || ex >= EXT - HH || ey < HH || ey >= EXT - HH) continue;
-        const size_t g = (size_t)(ty0 + ey - HH) * n + (tx0 + ex - HH);
-        rout[g] = sr[i];
-        cout[g] = cmp[k];
+    for (int k = 0; k < BPT; ++k) {
+        if ((binf[k] >> 13) <= (uint32_t)HB) continue;
+        const int b = t + k * THREADS;
+        const int bx = b % NBS, by = b / NBS;
+        const uint32_t g0 = at(ty0 + 2 * by - HH, tx0 + 2 * bx - HH), g1 = g0 + 4u * (uint32_t)n;
+        *(float2*)(rout + g0) = make_float2(r[k][0], r[k][1]);
+        *(float2*)(rout + g1) = make_float2(r[k][2], r[k][3]);
+        *(float2*)(cout + g0) = make_float2(cm[k][0], cm[k][1]);
+        *(float2*)(cout + g1) = make_float2(cm[k][2], cm[k][3]);
     }
     if constexpr (FUSED) {
         if (!A.do_coarse) return;
-        // one coarse EM step with the restricted noise Z (coarse tile + 1 halo cell), reusing LDS
+        // One coarse EM step with the restricted noise Z.  The block at (bx, by), block distance >= 1
+        // from the edge, holds the coarse cell (cx0 + bx - HB, cy0 + by - HB): together the coarse
+        // tile and a ring of one cell.  Its coarse density and fluxes go to the LDS slot of its
+        // first fine cell, so coarse neighbours sit two fine cells (two rows) apart.
         const size_t ncc = (size_t)nc * nc;
         const float* rcin = A.rhoc_in + sidx * ncc;
         const float* ccin = A.cmpc_in + sidx * ncc;
         float* rcout = A.rhoc_out + sidx * ncc;
         float* ccout = A.cmpc_out + sidx * ncc;
-        __syncthreads();
-        float* scr = sr;                 // [CEXT][CEXT]
-        float* scf0 = sf0;
-        float* scf1 = sf1;
-        for (int c = t; c < CEXT * CEXT; c += THREADS) {
-            const int ex = c % CEXT, ey = c / CEXT;
-            scr[c] = rcin[(size_t)wrapi(cy0 + ey - 1, nc) * nc + wrapi(cx0 + ex - 1, nc)];
-        }
-        __syncthreads();
-        // fluxes of the coarse cells in the halo region: block (bx, by) <-> coarse ext (bx - 1, by - 1)
         const float kc = A.kc;
+        // central fluxes: the last fine step's closing barrier already ordered its reads
+        if constexpr (FLUX != DK_FLUX_CENTRAL) __syncthreads();
+        float rc[BPT];
 #pragma unroll
         for (int k = 0; k < BPT; ++k) {
+            rc[k] = 0.f;
+            if ((binf[k] >> 13) < 2u) continue;
             const int b = t + k * THREADS;
-            if (b >= NBLK) continue;
             const int bx = b % NBS, by = b / NBS;
-            if (bx < 1 || bx >= NBS - 1 || by < 1 || by >= NBS - 1) continue;
-            const int ex = bx - 1, ey = by - 1;
-            const int c = ey * CEXT + ex;
-            const float rv = scr[c];
-            if (FLUX == DK_FLUX_CENTRAL) {
-                const float sq = psq(rv);
-                scf0[c] = sq * Z[k][0];
-                scf1[c] = sq * Z[k][1];
-            } else {
-                const float rx = ex + 1 < CEXT ? scr[c + 1] : rv;
-                const float ry = ey + 1 < CEXT ? scr[c + CEXT] : rv;
-                scf0[c] = psq(0.5f * (rv + rx)) * Z[k][0];
-                scf1[c] = psq(0.5f * (rv + ry)) * Z[k][1];
+            const int c0 = (int)(binf[k] & 0x1FFFu);
+            rc[k] = rcin[(size_t)wrapi(cy0 + by - HB, nc) * nc + wrapi(cx0 + bx - HB, nc)];
+            sr[c0] = rc[k];
+            if constexpr (FLUX == DK_FLUX_CENTRAL) {
+                const float sq = psq(rc[k]);
+                sf0[c0] = sq * Z[k][0];
+                sf1[c0] = sq * Z[k][1];
             }
         }
         __syncthreads();
-        for (int c = t; c < CT * CT; c += THREADS) {
-            const int ix = c % CT, iy = c / CT;
-            const int e = (iy + 1) * CEXT + (ix + 1);
-            const size_t g = (size_t)(cy0 + iy) * nc + (cx0 + ix);
-            const float rv = scr[e];
-            const float lap = fmaf(-4.0f, rv, (scr[e - 1] + scr[e + 1]) + (scr[e - CEXT] + scr[e + CEXT]));
+        if constexpr (FLUX != DK_FLUX_CENTRAL) {
+            // edge fluxes (the ring's outer ones read cells that are not coarse; no update reads them)
+#pragma unroll
+            for (int k = 0; k < BPT; ++k) {
+                if ((binf[k] >> 13) < 2u) continue;
+                const int c0 = (int)(binf[k] & 0x1FFFu);
+                sf0[c0] = psq(0.5f * (rc[k] + sr[c0 + 2])) * Z[k][0];
+                sf1[c0] = psq(0.5f * (rc[k] + sr[c0 + 2 * P])) * Z[k][1];
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int k = 0; k < BPT; ++k) {
+            if ((binf[k] >> 13) <= (uint32_t)HB) continue;
+            const int b = t + k * THREADS;
+            const int bx = b % NBS, by = b / NBS;
+            const int c0 = (int)(binf[k] & 0x1FFFu);
+            const size_t g = (size_t)(cy0 + by - HB) * nc + (cx0 + bx - HB);
             float div;
-            if (FLUX == DK_FLUX_CENTRAL) div = (scf0[e + 1] - scf0[e - 1]) + (scf1[e + CEXT] - scf1[e - CEXT]);
-            else div = (scf0[e] - scf0[e - 1]) + (scf1[e] - scf1[e - CEXT]);
-            const float d = fmaf(kc, div, a * lap);
-            const float cm = ccin[g];
-            const float y = d - cm;
-            const float tv = rv + y;
-            rcout[g] = tv;
-            ccout[g] = (tv - rv) - y;
+            if constexpr (FLUX == DK_FLUX_CENTRAL) div = (sf0[c0 + 2] - sf0[c0 - 2]) + (sf1[c0 + 2 * P] - sf1[c0 - 2 * P]);
+            else div = (sf0[c0] - sf0[c0 - 2]) + (sf1[c0] - sf1[c0 - 2 * P]);
+            float rv = rc[k], cmv = ccin[g];
+            em_cell(rv, cmv, sr[c0 - 2], sr[c0 + 2], sr[c0 - 2 * P], sr[c0 + 2 * P], div, a, kc);
+            rcout[g] = rv;
+            ccout[g] = cmv;
         }
     }
 }
