@@ -17,7 +17,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdk_mlmc.so")
 
 SOURCES = ["dk_kernels.hip", "dk_round.hip", "dk_stream.hip", "dk_fourier.hip", "dk_theta.hip", "dk_cnn.hip",
-           "dk_noalloc.hip", "dk_api.cpp"]
+           "dk_noalloc.hip", "dk_host_common.cpp", "dk_levels.cpp", "dk_tuning.cpp", "dk_rounds.cpp", "dk_alg1.cpp",
+           "dk_samplers.cpp", "dk_arena.cpp", "dk_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -75,7 +75,7 @@ hipError_t launch_meanfield_stream(int n, double a, int steps, double* buf0, dou
 hipError_t launch_inner_products(const double* rho, int n, const double* phi, int n_obs, double h2,
                                  double* out, hipStream_t s);
 
-// Host side of the allocation-free level batch (dk_api.cpp): samples [first, first + count) of
+// Host side of the allocation-free level batch (dk_arena.cpp): samples [first, first + count) of
 // resident level `level` (a pair for level >= 1) with every device buffer, the level tables and
 // the centring run included, carved from `arena` (device, arena_bytes, 256-byte aligned); returns a
 // dk status (DK_EINVAL when the tables and one chunk of per-sample values do not fit).

@@ -1,5 +1,5 @@
 // CPU stand-ins for the HIP runtime calls and the kernel launch layer (dk::launch_* and the
-// capability queries) that the host driver uses, for a sanitizer build of dk_api.cpp without a
+// capability queries) that the host driver uses, for a sanitizer build of the dk_*.cpp sources without a
 // GPU.  Test infrastructure only.
 //
 // Each stand-in kernel touches exactly the buffer extents the real kernel reads and writes

@@ -1,4 +1,4 @@
-// A CPU stand-in for the part of the HIP runtime API that the host driver (dk_api.cpp) calls,
+// A CPU stand-in for the part of the HIP runtime API that the host driver (the dk_*.cpp sources) calls,
 // so that the driver can be built with g++ under AddressSanitizer and UndefinedBehaviorSanitizer
 // and exercised without a GPU.  "Device" memory is host heap memory; work submitted to a stream
 // runs when it is submitted, except while the stream is being captured, when it is recorded and

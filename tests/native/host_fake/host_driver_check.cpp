@@ -1,4 +1,4 @@
-// Host-driver harness: dk_api.cpp built with g++ against the CPU stand-ins of fake_device.cpp,
+// Host-driver harness: the host sources (dk_*.cpp) built with g++ against the CPU stand-ins of fake_device.cpp,
 // run under AddressSanitizer and UndefinedBehaviorSanitizer.  Test infrastructure only.
 //
 // Scenarios (each names itself on stdout before it starts):

@@ -1,5 +1,6 @@
-"""The host driver (paper_2311_08872_amd/csrc/dk_api.cpp) built with g++ under AddressSanitizer and
-UndefinedBehaviorSanitizer against CPU stand-ins of the HIP runtime and of the kernel launch layer
+"""The host driver (the host sources in paper_2311_08872_amd/csrc: the C ABI in dk_api.cpp and the
+level, tuning, round, Algorithm-1, sampler and arena sources behind it) built with g++ under
+AddressSanitizer and UndefinedBehaviorSanitizer against CPU stand-ins of the HIP runtime and of the kernel launch layer
 (tests/native/host_fake), then driven through Algorithm 1 in every round mode (with the tile-shape
 tuner, small launch caps, a reused context whose buffers grow under a captured graph), the
 streaming path at every temporal depth and with its depth tuning, the allocation-free level batch on a
@@ -14,7 +15,9 @@ import pytest
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 FAKE = os.path.join(HERE, "native", "host_fake")
-API = os.path.join(os.path.dirname(HERE), "paper_2311_08872_amd", "csrc", "dk_api.cpp")
+CSRC = os.path.join(os.path.dirname(HERE), "paper_2311_08872_amd", "csrc")
+HOST_SOURCES = [os.path.join(CSRC, f) for f in ("dk_host_common.cpp", "dk_levels.cpp", "dk_tuning.cpp", "dk_rounds.cpp",
+                                                "dk_alg1.cpp", "dk_samplers.cpp", "dk_arena.cpp", "dk_api.cpp")]
 FLAGS = ["-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
          "-fno-sanitize-recover=undefined", "-I" + FAKE, "-Wall", "-Wno-unused-variable"]
 
@@ -25,7 +28,7 @@ def harness(tmp_path_factory):
         pytest.skip("g++ not available")
     out = tmp_path_factory.mktemp("host_fake")
     objs = []
-    srcs = [os.path.join(FAKE, "fake_device.cpp"), os.path.join(FAKE, "host_driver_check.cpp"), API]
+    srcs = [os.path.join(FAKE, "fake_device.cpp"), os.path.join(FAKE, "host_driver_check.cpp")] + HOST_SOURCES
     procs = []
     for s in srcs:
         o = str(out / (os.path.basename(s) + ".o"))
