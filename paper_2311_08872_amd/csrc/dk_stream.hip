@@ -116,7 +116,8 @@ __global__ void __launch_bounds__(Geo<D>::THREADS, Geo<D>::WAVES_PER_SIMD) strea
     const int nc = n / 2;
     const uint64_t sample = A.first + sidx;
     const size_t nn = (size_t)n * n;
-    // per-sample bases; cells are addressed by 32-bit byte offsets from them (n <= 32768)
+    // per-sample bases; cells are addressed by 32-bit byte offsets from them (4 n^2 < 2^32 for the
+    // grids up to 4096^2 that the library accepts)
     const char* rin = (const char*)(A.rho_in + sidx * nn);
     const char* cin = (const char*)(A.cmp_in + sidx * nn);
     char* rout = (char*)(A.rho_out + sidx * nn);
