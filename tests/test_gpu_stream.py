@@ -169,6 +169,34 @@ def test_stream_320_pair_odd_tile_count_all_depths():
     assert err <= 1e-5
 
 
+@pytest.mark.parametrize("flux", [W.FLUX_CENTRAL, W.FLUX_STAGGERED])
+def test_stream_single_paths_partial_last_launch(flux):
+    """Single paths on a streamed 256^2 level over 13 fine steps, so every depth but 1 ends on a
+    partial launch (4 + 4 + 4 + 1 at depth 4, 6 x 2 + 1 at depth 2, 8 + 5 at depth 8); every depth
+    gives the same per-sample values, which match the oracle (N = 1e4, as for the 320^2 pair)."""
+    p = W.config5(N=1e4).with_(n0=256, levels=1, flux=flux)
+    p = p.with_(T=p.tau(0) * 13, steps_policy=W.STEPS_EXACT)
+    assert p.n(0) == 256 and p.steps(0) == 13
+    banner(f"stream 256^2 single paths, 13 steps, flux={flux}")
+    ref = oracle.run_range(oracle.OracleProblem(p), 0, 2, 3, tag=W.TAG_MC, coupled=False)   # dk_mc_level's stream
+    vals = {}
+    for depth in (4, 1, 2, 8):
+        ctx = dk.Context(0)
+        ctx.set_stream_depth(depth)
+        _, ps = dk.mc_level(p, 0, 2, 3, per_sample=True, ctx=ctx)
+        torch.cuda.synchronize()
+        assert [s["rows"] for s in ctx.stats()] == [-depth]
+        vals[depth] = ps.cpu()
+        ctx.close()
+    for depth in (1, 2, 8):
+        assert torch.equal(vals[depth], vals[4]), depth
+    gpu = vals[4].numpy()
+    assert np.all(gpu[..., 1] == 0.0)
+    err = scaled_err(gpu[..., 0], ref[..., 0])
+    banner(f"max scaled error {err:.3g}")
+    assert err <= 1e-5
+
+
 def test_stream_4096_pair_largest_grid():
     """The largest grid the library accepts (4096^2 fine, 2048^2 coarse), one pair over 8 fine
     steps at depth 4 and at depth 1, against the oracle."""
