@@ -139,7 +139,8 @@ def test_stream_1024_pair_matches_oracle():
     assert float(rel.max()) <= 1e-5, rel.max()
 
 
-def test_stream_320_pair_odd_tile_count_all_depths():
+@pytest.mark.parametrize("flux", [W.FLUX_CENTRAL, W.FLUX_STAGGERED])
+def test_stream_320_pair_odd_tile_count_all_depths(flux):
     """A grid of 5 x 5 tiles (320^2 fine / 160^2 coarse): an odd number of tiles per side, and 75
     workgroups for 3 samples, so the numbering of workgroups by compute die takes its remainder
     branch.  12 fine steps: at depth 8 the second launch is a partial one (4 of 8 steps), at depths
@@ -148,10 +149,10 @@ def test_stream_320_pair_odd_tile_count_all_depths():
     order N^{-1/2} against L of order 1, so at config 5's N = 1e6 merely rounding the oracle's exact
     final field to FP32 moves these three samples by 7.9e-6 of their RMS (5e-7 at N = 1e5, 7e-7 at
     1e4), which would leave no room under the 1e-5 bar for the FP32 arithmetic itself."""
-    p = W.config5(N=1e4).with_(n0=160, levels=2)
+    p = W.config5(N=1e4).with_(n0=160, levels=2, flux=flux)
     p = p.with_(T=p.tau(1) * 12, steps_policy=W.STEPS_EXACT)
     assert p.n(1) == 320 and p.steps(1) == 12
-    banner("stream 320^2 pair (5 x 5 tiles) vs oracle, depths 4, 1, 2, 8")
+    banner(f"stream 320^2 pair (5 x 5 tiles) vs oracle, depths 4, 1, 2, 8, flux={flux}")
     ref = oracle.run_range(oracle.OracleProblem(p), 1, 5, 3)
     vals = {}
     for depth in (4, 1, 2, 8):
