@@ -198,6 +198,32 @@ def test_stream_single_paths_partial_last_launch(flux):
     assert err <= 1e-5
 
 
+def test_algorithm1_with_streamed_levels_matches_resident():
+    """Algorithm 1 on config 2 (eps = 1e-2) with the 64^2 and 128^2 levels routed through the streaming
+    kernel takes the same sample counts and reaches the same estimates as with the resident kernels:
+    the per-sample values are bit-identical, and only the grouping of the moment sums differs (the
+    streamed levels are merged in batches of up to 4096 samples), so the estimates agree to rounding."""
+    import math
+    p = W.config2(N=1e4).with_(seed=5)
+    banner("Algorithm 1, config 2, eps 1e-2: streamed 64^2 / 128^2 levels against resident")
+    res = []
+    for streamed in (False, True):
+        ctx = dk.Context(0)
+        ctx.set_streaming(streamed)
+        r = dk.estimate(p, 1e-2, ctx=ctx, round_mode=0)
+        rows = {s["level"]: s["rows"] for s in ctx.stats() if p.n(s["level"]) >= 64}
+        ctx.close()
+        assert rows, "the run must reach a 64^2 level"
+        assert all((v < 0) == streamed for v in rows.values()), rows
+        res.append(r)
+    a, b = res
+    assert a["L"] == b["L"] and a["M"] == b["M"]
+    for x, y in zip(a["estimate"], b["estimate"]):
+        assert math.isclose(x, y, rel_tol=1e-12, abs_tol=1e-15), (x, y)
+    for x, y in zip(a["Yhat"], b["Yhat"]):
+        assert math.isclose(x, y, rel_tol=1e-12, abs_tol=1e-15), (x, y)
+
+
 def test_stream_4096_pair_largest_grid():
     """The largest grid the library accepts (4096^2 fine, 2048^2 coarse), one pair over 8 fine
     steps at depth 4 and at depth 1, against the oracle."""
